@@ -1,0 +1,74 @@
+"""Uniform octree leaf assignment for synthetic inputs.
+
+Each element goes to the finest-level box that holds its centroid (the
+paper's element-to-box rule, Sec. 2 after Eq. (5), with the centroid as the
+element centre).  Only occupied boxes are kept, numbered in Morton order, with
+their centres and radii.  No part of the Q2X method is computed here.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class Boxes:
+    level: int
+    lo: float            # root cube is [lo, lo + 2*half]^3
+    half: float          # root half-side
+    h: float             # leaf box side
+    elem_box: np.ndarray     # [N] int32, index into the occupied-box list
+    center: np.ndarray       # [B, 3] float64
+    radius: np.ndarray       # [B] float64, half-diagonal sqrt(3) h / 2
+    morton: np.ndarray       # [B] int64 Morton code of each occupied box
+    counts: np.ndarray       # [B] elements per box
+
+    @property
+    def n_boxes(self) -> int:
+        return int(self.center.shape[0])
+
+
+def _spread3(x):
+    """Interleave the low 21 bits of x with two zero bits (Morton helper)."""
+    x = x.astype(np.uint64) & np.uint64(0x1FFFFF)
+    x = (x | (x << np.uint64(32))) & np.uint64(0x1F00000000FFFF)
+    x = (x | (x << np.uint64(16))) & np.uint64(0x1F0000FF0000FF)
+    x = (x | (x << np.uint64(8))) & np.uint64(0x100F00F00F00F00F)
+    x = (x | (x << np.uint64(4))) & np.uint64(0x10C30C30C30C30C3)
+    x = (x | (x << np.uint64(2))) & np.uint64(0x1249249249249249)
+    return x
+
+
+def morton3(ix, iy, iz):
+    return (_spread3(ix) | (_spread3(iy) << np.uint64(1)) | (_spread3(iz) << np.uint64(2))).astype(np.int64)
+
+
+def root_half_side(verts) -> float:
+    """Origin-centred root cube: [-1,1]^3 when every coordinate fits, else
+    the smallest origin-centred cube holding all vertices (tiny margin)."""
+    m = float(np.max(np.abs(verts))) if verts.size else 1.0
+    return 1.0 if m <= 1.0 else m * (1.0 + 1e-12)
+
+
+def assign(verts, elems, level: int, half: float | None = None) -> Boxes:
+    """Assign elements (rows of vertex indices) to occupied leaf boxes."""
+    verts = np.asarray(verts, dtype=np.float64)
+    elems = np.asarray(elems)
+    if half is None:
+        half = root_half_side(verts)
+    lo = -half
+    nside = 1 << level
+    h = 2.0 * half / nside
+    cen = verts[elems].mean(axis=1)
+    idx = np.clip(np.floor((cen - lo) / h).astype(np.int64), 0, nside - 1)
+    code = morton3(idx[:, 0], idx[:, 1], idx[:, 2])
+    ucode, inv, counts = np.unique(code, return_inverse=True, return_counts=True)
+    # decode box integer coordinates from any member element
+    first = np.zeros(ucode.shape[0], dtype=np.int64)
+    first[inv[::-1]] = np.arange(inv.shape[0])[::-1]
+    bidx = idx[first]
+    center = lo + (bidx + 0.5) * h
+    radius = np.full(ucode.shape[0], np.sqrt(3.0) * h / 2.0)
+    return Boxes(level=level, lo=lo, half=half, h=h, elem_box=inv.astype(np.int32), center=center,
+                 radius=radius, morton=ucode, counts=counts.astype(np.int64))
