@@ -1,0 +1,195 @@
+/*
+ * q2x.h -- C ABI of the MI355X Quadrature-to-Expansion (Q2X) library.
+ *
+ * For flat simplices with piecewise-constant density the library computes the
+ * Laplace multipole coefficients of each element about the centre of the leaf
+ * box that owns it, with the O(1)-per-moment recursions of Gumerov, Kaneko &
+ * Duraiswami (arXiv 2107.10942, Sec. 3.3-3.4, Eqs. (50)-(56)), and sums them
+ * into one expansion per box (Sec. 2, Eq. (5)).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every array argument is a DEVICE pointer owned by the caller.  The
+ *    library allocates nothing per call; scratch memory is the caller's
+ *    `workspace` of at least q2x_workspace_bytes(...) bytes (256-byte aligned).
+ *  - Calls are asynchronous on `stream` (a hipStream_t; NULL = default
+ *    stream).  Argument errors are returned synchronously; data errors are
+ *    reported through the device status word in the workspace (see
+ *    q2x_status_get), after the caller synchronises the stream.
+ *  - Sizes: n_elems < 2^31, n_boxes < 2^31, 0 <= p <= Q2X_P_MAX.
+ *  - Output `coeffs` is [n_boxes][(p+1)^2][2] doubles (re, im); coefficient
+ *    (n, m), -n <= m <= n, sits at index n*n + n + m.  Without
+ *    Q2X_ACCUMULATE every box in [0, n_boxes) is overwritten (empty boxes get
+ *    zeros); with it the new coefficients are added to what is there.
+ *  - Normalisation (`norm`):
+ *      Q2X_NORM_FMM    : F_n^m = sum_e sigma_e (1/4pi)(-1)^n int_e R_n^{-m}(y-c) dmu
+ *                        (Sec. 3.2, Eqs. (14),(20)), so that
+ *                        sum_{n<=p} sum_m F_n^m S_n^m(r - c) is the potential
+ *                        (Sec. 2, Eq. (5); Sec. 3.2, Eq. (13)).
+ *      Q2X_NORM_MOMENT : M_n^m = sum_e sigma_e int_e R_n^{m}(y-c) dmu
+ *                        = (-1)^{n+m} 4pi conj(F_n^m); M_0^0 = sum sigma*measure.
+ *    R_n^m, S_n^m are the solid harmonics of Sec. 3.2, Eq. (10).
+ *  - Element -> box: elem_box[e] in [0, n_boxes) names the leaf box whose
+ *    centre c = box_center[b] is the expansion centre (Sec. 2, after Eq. (5)).
+ *    Elements are grouped by box internally (stable counting sort, increasing
+ *    element index inside a box) unless Q2X_PRESORTED says elem_box is
+ *    already non-decreasing.  An id outside [0, n_boxes) sets
+ *    Q2X_FLAG_BAD_BOX and the element is skipped.
+ *  - box_radius[b] > 0 is the box radius rho used by Q2X_FP32_MIXED to scale
+ *    coordinates (y - c)/rho before the FP32 recursion; the FP64 result does not
+ *    depend on it.  rho <= 0 or non-finite sets Q2X_FLAG_BAD_RADIUS and the
+ *    box's elements are skipped (mixed precision only).
+ *  - Degenerate elements (zero length/area/volume) contribute exactly zero and
+ *    are counted.  Elements with non-finite coordinates or density set
+ *    Q2X_FLAG_NONFINITE and are skipped; vertex indices outside [0, n_verts)
+ *    set Q2X_FLAG_BAD_VERTEX and are skipped.  Nothing is ever written out of
+ *    bounds.
+ *  - Calls are reentrant when they use distinct workspaces; two calls that
+ *    share a workspace must be ordered on one stream.
+ */
+#ifndef Q2X_H
+#define Q2X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define Q2X_P_MAX 32
+
+typedef enum {
+  Q2X_OK = 0,
+  Q2X_ERR_ARG = -1,         /* null/misaligned pointer, negative size, bad enum */
+  Q2X_ERR_P_RANGE = -2,     /* p < 0 or p > Q2X_P_MAX */
+  Q2X_ERR_WORKSPACE = -3,   /* workspace too small or misaligned */
+  Q2X_ERR_HIP = -4,         /* a HIP runtime call failed */
+  Q2X_ERR_UNSUPPORTED = -5  /* valid request this build does not implement */
+} q2x_status;
+
+typedef enum { Q2X_TRI_SINGLE = 0, Q2X_TRI_DOUBLE = 1, Q2X_SEGMENT = 2, Q2X_TET = 3 } q2x_kind;
+typedef enum { Q2X_FP64 = 0, Q2X_FP32_MIXED = 1 } q2x_precision;
+typedef enum { Q2X_NORM_FMM = 0, Q2X_NORM_MOMENT = 1 } q2x_norm;
+
+enum {
+  Q2X_ACCUMULATE = 1u, /* add into coeffs instead of overwriting */
+  Q2X_PRESORTED = 2u   /* elem_box is non-decreasing: skip the bucketing sort */
+};
+
+/* Device status word bits (q2x_status_get). */
+enum {
+  Q2X_FLAG_BAD_BOX = 1u,
+  Q2X_FLAG_NONFINITE = 2u,
+  Q2X_FLAG_BAD_RADIUS = 4u,
+  Q2X_FLAG_BAD_VERTEX = 8u,
+  Q2X_FLAG_NOT_SORTED = 16u /* Q2X_PRESORTED given but elem_box decreases */
+};
+
+/* Bytes of workspace one call of this shape needs (0 on invalid arguments). */
+size_t q2x_workspace_bytes(int kind, int64_t n_elems, int64_t n_boxes, int p, int precision);
+
+/*
+ * Single-layer potential of flat triangles with constant density per
+ * triangle (Sec. 2, Eq. (1) first line; coefficients L of Sec. 3.2,
+ * Eqs. (14),(20)).  Recursion: vertex values q at x2 (Eqs. (40)-(41)), edge
+ * integrals j along x3->x2 (Lemma 3, Eq. (32)), surface integrals i coned from
+ * x1 (Lemma 2, Eq. (26)), in the m >= 0 form of Sec. 3.4, Eqs. (50)-(53).
+ *   verts   [n_verts][3] double     vertex coordinates
+ *   tris    [n_tris][3] int32       vertex indices (x1, x2, x3)
+ *   density [n_tris] double         sigma_e
+ *   elem_box[n_tris] int32          owning leaf box of each triangle
+ *   box_center [n_boxes][3] double, box_radius [n_boxes] double
+ */
+q2x_status q2x_tri_single(const double* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+                          const double* density, const int32_t* elem_box, const double* box_center,
+                          const double* box_radius, int64_t n_boxes, int p, int precision, int norm,
+                          unsigned flags, double* coeffs, void* workspace, size_t workspace_bytes,
+                          void* stream);
+
+/*
+ * Double-layer potential of flat triangles (Sec. 2, Eq. (1) second line;
+ * coefficients M of Sec. 3.2, Eqs. (14),(18),(20)), from the single-layer
+ * surface integrals of the previous degree (Sec. 3.4, Eq. (56)).  The normal
+ * is n = (x2-x1)x(x3-x1)/|.| (right-hand rule on the given vertex order).
+ * Same arguments as q2x_tri_single.
+ */
+q2x_status q2x_tri_double(const double* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+                          const double* density, const int32_t* elem_box, const double* box_center,
+                          const double* box_radius, int64_t n_boxes, int p, int precision, int norm,
+                          unsigned flags, double* coeffs, void* workspace, size_t workspace_bytes,
+                          void* stream);
+
+/*
+ * Line segments with constant scalar line density (the integrals K of Sec. 2,
+ * Eq. (3), one density component; Sec. 3.2, Eqs. (14),(20)).  Recursion:
+ * vertex values q at x2 and segment integrals p from x1 (Lemma 1, Eq. (25);
+ * Sec. 3.4, Eqs. (50)-(51)).
+ *   segs [n_segs][2] int32 vertex indices (x1, x2); other arguments as above.
+ */
+q2x_status q2x_segment(const double* verts, int64_t n_verts, const int32_t* segs, int64_t n_segs,
+                       const double* density, const int32_t* elem_box, const double* box_center,
+                       const double* box_radius, int64_t n_boxes, int p, int precision, int norm,
+                       unsigned flags, double* coeffs, void* workspace, size_t workspace_bytes,
+                       void* stream);
+
+/*
+ * Tetrahedra with constant charge (the volume integrals N of Sec. 2, Eq. (4);
+ * Sec. 3.2, Eqs. (14),(20)).  Recursion: q at x2, j along x3->x2, face
+ * integrals b coned from x4 (Lemma 5, Eq. (38)), volume integrals a coned from
+ * x1 (Lemma 4, Eq. (34)); Sec. 3.4, Eqs. (54)-(55).  J = |det| (orientation free).
+ *   tets [n_tets][4] int32 vertex indices (x1, x2, x3, x4); other arguments as above.
+ */
+q2x_status q2x_tet(const double* verts, int64_t n_verts, const int32_t* tets, int64_t n_tets,
+                   const double* density, const int32_t* elem_box, const double* box_center,
+                   const double* box_radius, int64_t n_boxes, int p, int precision, int norm,
+                   unsigned flags, double* coeffs, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * The bucketing step on its own: stable grouping of elements by leaf box
+ * (every element belongs to exactly one box, Sec. 2 after Eq. (5)).
+ *   elem_box  [n_elems] int32   box id of each element
+ *   perm      [n_elems] int32   out: element indices grouped by increasing box
+ *                               id, increasing element index inside a box; the
+ *                               elements with ids outside [0, n_boxes) follow
+ *                               the valid ones, in element order
+ *   box_start [n_boxes+1] int32 out: box b owns perm[box_start[b] .. box_start[b+1])
+ * Workspace: q2x_bucket_workspace_bytes(n_elems, n_boxes) bytes.  Ids outside
+ * [0, n_boxes) set Q2X_FLAG_BAD_BOX and are counted as skipped.
+ */
+size_t q2x_bucket_workspace_bytes(int64_t n_elems, int64_t n_boxes);
+q2x_status q2x_bucket(const int32_t* elem_box, int64_t n_elems, int64_t n_boxes, int32_t* perm, int32_t* box_start,
+                      void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Read the device status word of the last call that used `workspace`
+ * (synchronises `stream`).  device_flags: OR of Q2X_FLAG_*; n_degenerate:
+ * number of zero-measure elements; n_skipped: elements skipped for bad box,
+ * vertex index, radius or non-finite data.  Either output may be NULL.
+ */
+q2x_status q2x_status_get(const void* workspace, void* stream, uint32_t* device_flags, int64_t* n_degenerate,
+                          int64_t* n_skipped);
+
+/* Human-readable name of a q2x_status value. */
+const char* q2x_status_string(int status);
+
+/*
+ * Kernel timing for measurement.  When enabled, each call records HIP events
+ * around its recursion kernel on the call's stream; q2x_profile_read
+ * synchronises those events and returns the summed duration (ms) and the
+ * launch count since the last reset, for the recursion kernel and for the
+ * whole call (bucketing included).
+ */
+void q2x_profile_enable(int on);
+void q2x_profile_reset(void);
+q2x_status q2x_profile_read(double* recursion_ms, int64_t* recursion_launches, double* call_ms,
+                            int64_t* calls);
+
+/* Library version string. */
+const char* q2x_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* Q2X_H */

@@ -1,0 +1,86 @@
+"""Build the gfx950 Q2X library (``libq2x.so``) in-tree with hipcc.
+
+Every HIP source is compiled for gfx950 only.  The eight tile-kernel
+instantiation units (4 element kinds x 2 precisions) are large, fully
+unrolled translation units, so they compile in parallel.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libq2x.so")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+# -packed-fp32-ops: keep the compiler from emitting packed FP32 VALU ops.
+COMMON = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-I", os.path.join(HERE, "..", "include")]
+
+SIMPLE = ["q2x_api.hip", "q2x_bucket.hip", "q2x_dispatch.hip"]
+INST = [(k, f) for k in range(4) for f in (0, 1)]
+
+
+def _units():
+    units = []
+    for src in SIMPLE:
+        obj = os.path.join(BUILD, src.replace(".hip", ".o"))
+        units.append((obj, [os.path.join(CSRC, src)], []))
+    for k, f in INST:
+        obj = os.path.join(BUILD, f"q2x_inst_k{k}_f{f}.o")
+        units.append((obj, [os.path.join(CSRC, "q2x_inst.hip")], [f"-DQ2X_INST_KIND={k}", f"-DQ2X_INST_F32={f}"]))
+    return units
+
+
+def _headers():
+    return [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".hpp")] + \
+        [os.path.join(HERE, "..", "include", "q2x.h")]
+
+
+def _stale(obj, srcs):
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(s) > t for s in list(srcs) + _headers())
+
+
+def _compile(unit, verbose):
+    obj, srcs, defs = unit
+    cmd = [HIPCC] + COMMON + defs + ["-c", srcs[0], "-o", obj + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {srcs[0]} {defs}:\n{r.stderr[-4000:]}")
+    os.replace(obj + ".tmp", obj)
+    return obj
+
+
+def build(force: bool = True, verbose: bool = False, jobs: int | None = None) -> str:
+    """Compile (all units when force, else only stale ones) and link libq2x.so."""
+    os.makedirs(BUILD, exist_ok=True)
+    units = _units()
+    todo = [u for u in units if force or _stale(u[0], u[1])]
+    jobs = jobs or min(8, os.cpu_count() or 4)
+    if todo:
+        # largest units first
+        todo.sort(key=lambda u: 0 if "inst" in u[0] else 1)
+        with ThreadPoolExecutor(max_workers=jobs) as ex:
+            list(ex.map(lambda u: _compile(u, verbose), todo))
+    objs = [u[0] for u in units]
+    if todo or not os.path.exists(LIB):
+        cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(force="--force" in sys.argv, verbose=True))

@@ -1,0 +1,340 @@
+// q2x_api.hip -- C ABI entry points: argument checks, workspace layout, the
+// launch sequence of one call (status clear -> bucketing -> recursion tiles ->
+// fix-up of boxes cut by tile edges), status readback and kernel timing.
+#include <math.h>
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+#include "q2x_internal.hpp"
+
+namespace q2x {
+
+hipError_t bucket_elements(const int32_t* elem_box, int64_t n, int64_t nb, int32_t* scratch, int32_t* box_start,
+                           Status* status, hipStream_t s, const int32_t** keys_out, const int32_t** perm_out);
+hipError_t presorted_bounds(const int32_t* elem_box, int64_t n, int64_t nb, int32_t* box_start, Status* status,
+                            hipStream_t s);
+hipError_t clear_status(Status* st, hipStream_t s);
+hipError_t copy_words(int32_t* dst, const int32_t* src, int64_t n, hipStream_t s);
+size_t bucket_scratch_bytes(int64_t n, int64_t nb);
+
+// Boxes whose elements span more than one tile: sum the per-tile partials in
+// tile order, finalise and store.  Empty boxes: zeros (unless accumulating).
+// One wavefront per box; grid-stride over boxes.
+__global__ __launch_bounds__(256) void q2x_fixup_kernel(FixupArgs f) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int ncoef = (f.p + 1) * (f.p + 1);
+  const int nct_out = tri(f.p + 1);
+  const int NCT = tri(f.P + 1);
+  for (int64_t b = wave; b < f.n_boxes; b += nwaves) {
+    const int64_t s = f.box_start[b], t = f.box_start[b + 1];
+    double* row = f.coeffs + b * (int64_t)ncoef * 2;
+    if (t <= s) {
+      if (!f.accumulate)
+        for (int i = lane; i < 2 * ncoef; i += 64) row[i] = 0.0;
+      continue;
+    }
+    const int64_t t0 = s / kTile, t1 = (t - 1) / kTile;
+    if (t0 == t1) continue;  // finished by the tile kernel
+    double rho = 1.0;
+    if (f.scaled) rho = f.box_radius[b];
+    for (int g = lane; g < nct_out; g += 64) {
+      double ar = 0.0, ai = 0.0;
+      for (int64_t tt = t0; tt <= t1; ++tt) {
+        const int slot = (tt == t0 && s != t0 * kTile) ? 1 : 0;
+        const double* pp = f.partials + ((tt * 2 + slot) * (int64_t)NCT + g) * 2;
+        ar += pp[0];
+        ai += pp[1];
+      }
+      int n, m;
+      tri_nm(g, n, m);
+      const double rk = f.scaled ? ipow_d(rho, n - f.double_layer) : 1.0;
+      finalize_store(row, n, m, ar, ai, rk, f.norm, f.accumulate);
+    }
+  }
+}
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+struct Layout {
+  size_t status, box_start, sort, partials, total;
+};
+
+Layout layout(int64_t n, int64_t nb, int P) {
+  Layout L;
+  size_t off = 0;
+  L.status = off;
+  off += align_up(sizeof(Status));
+  L.box_start = off;
+  off += align_up((size_t)(nb + 1) * sizeof(int32_t));
+  L.sort = off;
+  off += align_up(bucket_scratch_bytes(n, nb));
+  L.partials = off;
+  const int64_t ntiles = (n + kTile - 1) / kTile;
+  off += align_up((size_t)ntiles * 2 * (size_t)tri(P + 1) * 2 * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+int verts_per_kind(int kind) {
+  switch (kind) {
+    case Q2X_SEGMENT: return 2;
+    case Q2X_TET: return 4;
+    default: return 3;
+  }
+}
+
+// ---- kernel timing (measurement aid)
+struct Prof {
+  std::mutex mu;
+  bool on = false;
+  struct Ev {
+    hipEvent_t a, b, c;  // call start, recursion start, recursion end (call end = c after fixup? no: d)
+    hipEvent_t d;
+  };
+  std::vector<Ev> evs;
+  std::vector<Ev> pool;
+};
+Prof& prof() {
+  static Prof p;
+  return p;
+}
+
+Prof::Ev get_ev() {
+  Prof& P = prof();
+  if (!P.pool.empty()) {
+    Prof::Ev e = P.pool.back();
+    P.pool.pop_back();
+    return e;
+  }
+  Prof::Ev e;
+  hipEventCreate(&e.a);
+  hipEventCreate(&e.b);
+  hipEventCreate(&e.c);
+  hipEventCreate(&e.d);
+  return e;
+}
+
+q2x_status run(int kind, const double* verts, int64_t n_verts, const int32_t* elems, int64_t n_elems,
+               const double* density, const int32_t* elem_box, const double* box_center, const double* box_radius,
+               int64_t n_boxes, int p, int prec, int norm, unsigned flags, double* coeffs, void* workspace,
+               size_t workspace_bytes, void* stream) {
+  if (p < 0 || p > Q2X_P_MAX) return Q2X_ERR_P_RANGE;
+  if (n_verts < 0 || n_elems < 0 || n_boxes < 0 || n_elems >= ((int64_t)1 << 31) - 64 ||
+      n_boxes >= ((int64_t)1 << 31) - 1 || n_verts >= ((int64_t)1 << 31))
+    return Q2X_ERR_ARG;
+  if (prec != Q2X_FP64 && prec != Q2X_FP32_MIXED) return Q2X_ERR_ARG;
+  if (norm != Q2X_NORM_FMM && norm != Q2X_NORM_MOMENT) return Q2X_ERR_ARG;
+  if (flags & ~(unsigned)(Q2X_ACCUMULATE | Q2X_PRESORTED)) return Q2X_ERR_ARG;
+  if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return Q2X_ERR_WORKSPACE;
+  if (n_boxes > 0 && (!coeffs || !box_center || !box_radius)) return Q2X_ERR_ARG;
+  if (n_elems > 0 && (!verts || !elems || !density || !elem_box)) return Q2X_ERR_ARG;
+  if (((uintptr_t)coeffs % 8) || ((uintptr_t)verts % 8) || ((uintptr_t)density % 8) ||
+      ((uintptr_t)box_center % 8) || ((uintptr_t)box_radius % 8) || ((uintptr_t)elems % 4) ||
+      ((uintptr_t)elem_box % 4))
+    return Q2X_ERR_ARG;
+  const int P = bucket_order(p);
+  if (P < 0) return Q2X_ERR_UNSUPPORTED;
+  const Layout L = layout(n_elems, n_boxes, P);
+  if (workspace_bytes < L.total) return Q2X_ERR_WORKSPACE;
+
+  hipStream_t s = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  Status* st = (Status*)(ws + L.status);
+  int32_t* box_start = (int32_t*)(ws + L.box_start);
+  int32_t* sort_scratch = (int32_t*)(ws + L.sort);
+  double* partials = (double*)(ws + L.partials);
+
+  Prof& PR = prof();
+  Prof::Ev ev{};
+  bool timing = false;
+  {
+    std::lock_guard<std::mutex> g(PR.mu);
+    timing = PR.on;
+    if (timing) ev = get_ev();
+  }
+  if (timing) hipEventRecord(ev.a, s);
+
+  if (clear_status(st, s) != hipSuccess) return Q2X_ERR_HIP;
+  const int32_t* keys = elem_box;
+  const int32_t* perm = nullptr;
+  hipError_t err;
+  if (flags & Q2X_PRESORTED) {
+    err = presorted_bounds(elem_box, n_elems, n_boxes, box_start, st, s);
+  } else {
+    err = bucket_elements(elem_box, n_elems, n_boxes, sort_scratch, box_start, st, s, &keys, &perm);
+  }
+  if (err != hipSuccess) return Q2X_ERR_HIP;
+
+  TileArgs a;
+  a.verts = verts;
+  a.elems = elems;
+  a.density = density;
+  a.keys = keys;
+  a.perm = perm;
+  a.box_center = box_center;
+  a.box_radius = box_radius;
+  a.box_start = box_start;
+  a.coeffs = coeffs;
+  a.partials = partials;
+  a.status = st;
+  a.n_verts = n_verts;
+  a.n_pos = n_elems;
+  a.n_boxes = n_boxes;
+  a.p = p;
+  a.norm = norm;
+  a.accumulate = (flags & Q2X_ACCUMULATE) ? 1 : 0;
+  const int64_t n_tiles = (n_elems + kTile - 1) / kTile;
+  if (timing) hipEventRecord(ev.b, s);
+  if (n_tiles > 0) {
+    err = launch_tiles(kind, prec, P, a, n_tiles, s);
+    if (err != hipSuccess) return Q2X_ERR_HIP;
+  }
+  if (timing) hipEventRecord(ev.c, s);
+  if (n_boxes > 0) {
+    FixupArgs f;
+    f.box_start = box_start;
+    f.box_radius = box_radius;
+    f.partials = partials;
+    f.coeffs = coeffs;
+    f.n_boxes = n_boxes;
+    f.p = p;
+    f.P = P;
+    f.norm = norm;
+    f.accumulate = a.accumulate;
+    f.scaled = (prec == Q2X_FP32_MIXED) ? 1 : 0;
+    f.double_layer = (kind == Q2X_TRI_DOUBLE) ? 1 : 0;
+    const int64_t waves = n_boxes;
+    int64_t blocks = (waves + 3) / 4;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(q2x_fixup_kernel, dim3((unsigned)blocks), dim3(256), 0, s, f);
+    if (hipGetLastError() != hipSuccess) return Q2X_ERR_HIP;
+  }
+  if (timing) {
+    hipEventRecord(ev.d, s);
+    std::lock_guard<std::mutex> g(PR.mu);
+    PR.evs.push_back(ev);
+  }
+  return Q2X_OK;
+}
+
+}  // namespace
+}  // namespace q2x
+
+using namespace q2x;
+
+extern "C" {
+
+size_t q2x_workspace_bytes(int kind, int64_t n_elems, int64_t n_boxes, int p, int precision) {
+  if (kind < 0 || kind > 3 || n_elems < 0 || n_boxes < 0 || p < 0 || p > Q2X_P_MAX) return 0;
+  if (precision != Q2X_FP64 && precision != Q2X_FP32_MIXED) return 0;
+  const int P = bucket_order(p);
+  if (P < 0) return 0;
+  return layout(n_elems, n_boxes, P).total;
+}
+
+#define Q2X_ENTRY(name, KIND)                                                                                      \
+  q2x_status name(const double* verts, int64_t n_verts, const int32_t* el, int64_t n_el, const double* density,   \
+                  const int32_t* elem_box, const double* box_center, const double* box_radius, int64_t n_boxes,  \
+                  int p, int precision, int norm, unsigned flags, double* coeffs, void* workspace,                \
+                  size_t workspace_bytes, void* stream) {                                                         \
+    return run(KIND, verts, n_verts, el, n_el, density, elem_box, box_center, box_radius, n_boxes, p, precision,  \
+               norm, flags, coeffs, workspace, workspace_bytes, stream);                                          \
+  }
+
+Q2X_ENTRY(q2x_tri_single, Q2X_TRI_SINGLE)
+Q2X_ENTRY(q2x_tri_double, Q2X_TRI_DOUBLE)
+Q2X_ENTRY(q2x_segment, Q2X_SEGMENT)
+Q2X_ENTRY(q2x_tet, Q2X_TET)
+
+size_t q2x_bucket_workspace_bytes(int64_t n_elems, int64_t n_boxes) {
+  if (n_elems < 0 || n_boxes < 0) return 0;
+  return align_up(sizeof(Status)) + align_up(bucket_scratch_bytes(n_elems, n_boxes));
+}
+
+q2x_status q2x_bucket(const int32_t* elem_box, int64_t n_elems, int64_t n_boxes, int32_t* perm, int32_t* box_start,
+                      void* workspace, size_t workspace_bytes, void* stream) {
+  if (n_elems < 0 || n_boxes < 0 || n_elems >= ((int64_t)1 << 31) - 64 || n_boxes >= ((int64_t)1 << 31) - 1)
+    return Q2X_ERR_ARG;
+  if (!box_start || (n_elems > 0 && (!elem_box || !perm))) return Q2X_ERR_ARG;
+  if (((uintptr_t)elem_box % 4) || ((uintptr_t)perm % 4) || ((uintptr_t)box_start % 4)) return Q2X_ERR_ARG;
+  if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return Q2X_ERR_WORKSPACE;
+  if (workspace_bytes < q2x_bucket_workspace_bytes(n_elems, n_boxes)) return Q2X_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  Status* st = (Status*)workspace;
+  int32_t* scratch = (int32_t*)((char*)workspace + align_up(sizeof(Status)));
+  if (clear_status(st, s) != hipSuccess) return Q2X_ERR_HIP;
+  const int32_t* keys = nullptr;
+  const int32_t* pm = nullptr;
+  if (bucket_elements(elem_box, n_elems, n_boxes, scratch, box_start, st, s, &keys, &pm) != hipSuccess)
+    return Q2X_ERR_HIP;
+  if (n_elems > 0 && copy_words(perm, pm, n_elems, s) != hipSuccess) return Q2X_ERR_HIP;
+  return Q2X_OK;
+}
+
+q2x_status q2x_status_get(const void* workspace, void* stream, uint32_t* device_flags, int64_t* n_degenerate,
+                          int64_t* n_skipped) {
+  if (!workspace) return Q2X_ERR_ARG;
+  Status h;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync(&h, workspace, sizeof(Status), hipMemcpyDeviceToHost, s) != hipSuccess) return Q2X_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return Q2X_ERR_HIP;
+  if (device_flags) *device_flags = h.flags;
+  if (n_degenerate) *n_degenerate = (int64_t)h.n_degenerate;
+  if (n_skipped) *n_skipped = (int64_t)h.n_skipped;
+  return Q2X_OK;
+}
+
+const char* q2x_status_string(int status) {
+  switch (status) {
+    case Q2X_OK: return "Q2X_OK";
+    case Q2X_ERR_ARG: return "Q2X_ERR_ARG: invalid argument";
+    case Q2X_ERR_P_RANGE: return "Q2X_ERR_P_RANGE: p outside [0, Q2X_P_MAX]";
+    case Q2X_ERR_WORKSPACE: return "Q2X_ERR_WORKSPACE: workspace missing, misaligned or too small";
+    case Q2X_ERR_HIP: return "Q2X_ERR_HIP: HIP runtime error";
+    case Q2X_ERR_UNSUPPORTED: return "Q2X_ERR_UNSUPPORTED";
+    default: return "unknown q2x_status";
+  }
+}
+
+void q2x_profile_enable(int on) {
+  Prof& P = prof();
+  std::lock_guard<std::mutex> g(P.mu);
+  P.on = (on != 0);
+}
+
+void q2x_profile_reset(void) {
+  Prof& P = prof();
+  std::lock_guard<std::mutex> g(P.mu);
+  for (auto& e : P.evs) P.pool.push_back(e);
+  P.evs.clear();
+}
+
+q2x_status q2x_profile_read(double* recursion_ms, int64_t* recursion_launches, double* call_ms, int64_t* calls) {
+  Prof& P = prof();
+  std::lock_guard<std::mutex> g(P.mu);
+  double rec = 0.0, tot = 0.0;
+  for (auto& e : P.evs) {
+    if (hipEventSynchronize(e.d) != hipSuccess) return Q2X_ERR_HIP;
+    float a = 0.f, b = 0.f;
+    if (hipEventElapsedTime(&a, e.b, e.c) != hipSuccess) return Q2X_ERR_HIP;
+    if (hipEventElapsedTime(&b, e.a, e.d) != hipSuccess) return Q2X_ERR_HIP;
+    rec += a;
+    tot += b;
+  }
+  if (recursion_ms) *recursion_ms = rec;
+  if (recursion_launches) *recursion_launches = (int64_t)P.evs.size();
+  if (call_ms) *call_ms = tot;
+  if (calls) *calls = (int64_t)P.evs.size();
+  return Q2X_OK;
+}
+
+const char* q2x_version(void) { return "q2x-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,168 @@
+// q2x_internal.hpp -- shared device-side definitions of the Q2X library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/q2x.h"
+
+namespace q2x {
+
+constexpr int kTile = 64;            // elements per wavefront tile (one lane per element)
+constexpr int kWave = 64;            // CDNA wavefront width
+constexpr double kInv4Pi = 0.07957747154594766788;  // 1/(4 pi)
+constexpr double k4Pi = 12.566370614359172954;
+
+// Status block at the head of every workspace.
+struct Status {
+  uint32_t flags;
+  uint32_t pad;
+  unsigned long long n_degenerate;
+  unsigned long long n_skipped;
+  unsigned long long reserved[5];
+};
+static_assert(sizeof(Status) == 64, "status block is 64 bytes");
+
+// Number of m >= 0 ("tilde") coefficients of degrees 0..n-1.
+__host__ __device__ constexpr int tri(int n) { return n * (n + 1) / 2; }
+
+// Arguments of the recursion + reduction kernel.
+struct TileArgs {
+  const double* verts;
+  const int32_t* elems;
+  const double* density;
+  const int32_t* keys;       // box id of each sorted position (elem_box itself when presorted)
+  const int32_t* perm;       // sorted position -> element index (nullptr: identity)
+  const double* box_center;
+  const double* box_radius;
+  const int32_t* box_start;  // [n_boxes + 1] start position of each box
+  double* coeffs;            // [n_boxes][(p+1)^2][2]
+  double* partials;          // [n_tiles][2][tri(P+1)][2] raw sums of boxes cut by tile edges
+  Status* status;
+  int64_t n_verts;
+  int64_t n_pos;             // number of positions covered by tiles (= n_elems)
+  int64_t n_boxes;
+  int p;                     // requested order (<= template P)
+  int norm;
+  int accumulate;
+};
+
+// Arguments of the fix-up kernel (boxes cut by tile edges, empty boxes).
+struct FixupArgs {
+  const int32_t* box_start;
+  const double* box_radius;
+  const double* partials;
+  double* coeffs;
+  int64_t n_boxes;
+  int p;
+  int P;                     // bucket order the partials were laid out for
+  int norm;
+  int accumulate;
+  int scaled;                // 1: coordinates were divided by rho (mixed precision)
+  int double_layer;          // 1: degree n scales as rho^(n-1)
+};
+
+// Logical tile of a workgroup: the hardware deals workgroups round-robin to
+// the 8 XCDs (each with its own L2); give every XCD one contiguous range of
+// tiles so that neighbouring tiles, which share vertices and box data, hit
+// the same L2.
+__device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t nblk) {
+  const int64_t q = nblk / 8, r = nblk % 8;
+  const int64_t x = bid % 8, k = bid / 8;
+  return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+// rho^k by binary powering (k >= 0).
+__device__ __forceinline__ double ipow_d(double rho, int k) {
+  double r = 1.0, b = rho;
+  while (k > 0) {
+    if (k & 1) r *= b;
+    b *= b;
+    k >>= 1;
+  }
+  return r;
+}
+
+// Turn the raw tilde box sum T_n^m (sum_e s_e t~_{e,n}^m, m >= 0) into the two
+// output coefficients and store (or add) them.
+//   FMM   : F_n^{m}  = (-1)^n rho^k i^{-m} conj(T),  F_n^{-m} = (-1)^n rho^k i^{-m} T
+//   MOMENT: M_n^{m}  = (-1)^m 4pi rho^k i^{m} T,     M_n^{-m} = (-1)^m 4pi rho^k i^{m} conj(T)
+// (tilde <-> plain: Sec. 3.4, Eqs. (47),(49); symmetry Eq. (12); weights Eq. (20)).
+__device__ __forceinline__ void finalize_store(double* row, int n, int m, double tr, double ti, double rho_k,
+                                               int norm, int accumulate) {
+  double a, b;  // value for +m
+  double c, d;  // value for -m
+  if (norm == Q2X_NORM_FMM) {
+    const double base = ((n & 1) ? -rho_k : rho_k);
+    // i^{-m}: m%4 = 0 -> 1, 1 -> -i, 2 -> -1, 3 -> i
+    const double xr = base * tr, xi = base * ti;  // base * T
+    double pr, pi;                                 // i^{-m} * (base*T)
+    switch (m & 3) {
+      case 0: pr = xr; pi = xi; break;
+      case 1: pr = xi; pi = -xr; break;
+      case 2: pr = -xr; pi = -xi; break;
+      default: pr = -xi; pi = xr; break;
+    }
+    // i^{-m} conj(base*T)
+    double qr, qi;
+    switch (m & 3) {
+      case 0: qr = xr; qi = -xi; break;
+      case 1: qr = -xi; qi = -xr; break;
+      case 2: qr = -xr; qi = xi; break;
+      default: qr = xi; qi = xr; break;
+    }
+    a = qr; b = qi; c = pr; d = pi;
+  } else {
+    const double base = ((m & 1) ? -k4Pi : k4Pi) * rho_k;
+    const double xr = base * tr, xi = base * ti;
+    double pr, pi;  // i^{m} * (base*T)
+    switch (m & 3) {
+      case 0: pr = xr; pi = xi; break;
+      case 1: pr = -xi; pi = xr; break;
+      case 2: pr = -xr; pi = -xi; break;
+      default: pr = xi; pi = -xr; break;
+    }
+    double qr, qi;  // i^{m} * conj(base*T)
+    switch (m & 3) {
+      case 0: qr = xr; qi = -xi; break;
+      case 1: qr = xi; qi = xr; break;
+      case 2: qr = -xr; qi = xi; break;
+      default: qr = -xi; qi = -xr; break;
+    }
+    a = pr; b = pi; c = qr; d = qi;
+  }
+  const int ip = n * n + n + m;
+  if (m == 0) {
+    b = 0.0;  // F_n^0 is real; its imaginary part is round-off
+    if (accumulate) { a += row[2 * ip]; b += row[2 * ip + 1]; }
+    row[2 * ip] = a;
+    row[2 * ip + 1] = b;
+    return;
+  }
+  const int im = n * n + n - m;
+  if (accumulate) {
+    a += row[2 * ip]; b += row[2 * ip + 1];
+    c += row[2 * im]; d += row[2 * im + 1];
+  }
+  row[2 * ip] = a;
+  row[2 * ip + 1] = b;
+  row[2 * im] = c;
+  row[2 * im + 1] = d;
+}
+
+// Degree and order of the g-th tilde coefficient (g = tri(n) + m).
+__device__ __forceinline__ void tri_nm(int g, int& n, int& m) {
+  int nn = (int)((__fsqrt_rn(8.0f * (float)g + 1.0f) - 1.0f) * 0.5f);
+  while (tri(nn + 1) <= g) ++nn;
+  while (tri(nn) > g) --nn;
+  n = nn;
+  m = g - tri(nn);
+}
+
+}  // namespace q2x
+
+// Host-side launchers implemented in the per-kind translation units.
+namespace q2x {
+hipError_t launch_tiles(int kind, int prec, int P, const TileArgs& a, int64_t n_tiles, hipStream_t s);
+int bucket_order(int p);  // smallest compiled bucket >= p (or -1)
+}  // namespace q2x

@@ -1,0 +1,202 @@
+"""Python binding of the Q2X C ABI (``include/q2x.h``) -- argument marshalling only.
+
+Every step of the computation runs in the HIP library ``libq2x.so``; torch is
+used only to own device memory and to name the stream.  If the library has not
+been built this module raises -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libq2x.so")
+
+TRI_SINGLE, TRI_DOUBLE, SEGMENT, TET = 0, 1, 2, 3
+KIND_NAMES = {TRI_SINGLE: "tri_single", TRI_DOUBLE: "tri_double", SEGMENT: "segment", TET: "tet"}
+VERTS_PER_KIND = {TRI_SINGLE: 3, TRI_DOUBLE: 3, SEGMENT: 2, TET: 4}
+FP64, FP32_MIXED = 0, 1
+NORM_FMM, NORM_MOMENT = 0, 1
+ACCUMULATE, PRESORTED = 1, 2
+P_MAX = 32
+FLAG_BAD_BOX, FLAG_NONFINITE, FLAG_BAD_RADIUS, FLAG_BAD_VERTEX, FLAG_NOT_SORTED = 1, 2, 4, 8, 16
+EXPORTS = ("q2x_workspace_bytes", "q2x_bucket_workspace_bytes", "q2x_bucket", "q2x_tri_single", "q2x_tri_double", "q2x_segment", "q2x_tet",
+           "q2x_status_get", "q2x_status_string", "q2x_profile_enable", "q2x_profile_reset",
+           "q2x_profile_read", "q2x_version")
+
+
+class Q2XError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """Load libq2x.so (raises Q2XError if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise Q2XError(f"{LIB_PATH} is missing: build it with paper_2107_10942_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, ci, cu, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_uint, ctypes.c_size_t
+        L.q2x_workspace_bytes.argtypes = [ci, i64, i64, ci, ci]
+        L.q2x_workspace_bytes.restype = sz
+        for name in ("q2x_tri_single", "q2x_tri_double", "q2x_segment", "q2x_tet"):
+            f = getattr(L, name)
+            f.argtypes = [vp, i64, vp, i64, vp, vp, vp, vp, i64, ci, ci, ci, cu, vp, vp, sz, vp]
+            f.restype = ci
+        L.q2x_bucket_workspace_bytes.argtypes = [i64, i64]
+        L.q2x_bucket_workspace_bytes.restype = sz
+        L.q2x_bucket.argtypes = [vp, i64, i64, vp, vp, vp, sz, vp]
+        L.q2x_bucket.restype = ci
+        L.q2x_status_get.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(ctypes.c_int64)]
+        L.q2x_status_get.restype = ci
+        L.q2x_status_string.argtypes = [ci]
+        L.q2x_status_string.restype = ctypes.c_char_p
+        L.q2x_profile_enable.argtypes = [ci]
+        L.q2x_profile_enable.restype = None
+        L.q2x_profile_reset.argtypes = []
+        L.q2x_profile_reset.restype = None
+        L.q2x_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+        L.q2x_profile_read.restype = ci
+        L.q2x_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise Q2XError(lib().q2x_status_string(rc).decode())
+
+
+def _ptr(t, dtype, name):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise Q2XError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise Q2XError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise Q2XError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def workspace_bytes(kind, n_elems, n_boxes, p, precision=FP32_MIXED) -> int:
+    return int(lib().q2x_workspace_bytes(kind, n_elems, n_boxes, p, precision))
+
+
+def alloc_workspace(kind, n_elems, n_boxes, p, precision=FP32_MIXED, device=None):
+    nbytes = workspace_bytes(kind, n_elems, n_boxes, p, precision)
+    if nbytes == 0:
+        raise Q2XError("invalid workspace request")
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device or "cuda")
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + nbytes]
+
+
+def run(kind, verts, elems, density, elem_box, box_center, box_radius, p, precision=FP32_MIXED,
+        norm=NORM_FMM, accumulate=False, presorted=False, out=None, workspace=None, stream=None):
+    """Q2X for one mesh of one element kind; returns out [B, (p+1)^2, 2] float64."""
+    n_el = int(elems.shape[0]) if elems is not None else 0
+    nb = int(box_center.shape[0])
+    if elems is not None and elems.dim() == 2 and elems.shape[1] != VERTS_PER_KIND[kind]:
+        raise Q2XError(f"elements of kind {KIND_NAMES[kind]} need {VERTS_PER_KIND[kind]} vertices")
+    if out is None:
+        out = torch.empty((nb, (p + 1) ** 2, 2), dtype=torch.float64, device=verts.device)
+    elif tuple(out.shape) != (nb, (p + 1) ** 2, 2):
+        raise Q2XError(f"out must have shape {(nb, (p + 1) ** 2, 2)}")
+    if workspace is None:
+        workspace = alloc_workspace(kind, n_el, nb, p, precision, device=verts.device)
+    flags = (ACCUMULATE if accumulate else 0) | (PRESORTED if presorted else 0)
+    fn = getattr(lib(), "q2x_" + KIND_NAMES[kind])
+    rc = fn(_ptr(verts, torch.float64, "verts"), int(verts.shape[0]),
+            _ptr(elems, torch.int32, "elems"), n_el,
+            _ptr(density, torch.float64, "density"), _ptr(elem_box, torch.int32, "elem_box"),
+            _ptr(box_center, torch.float64, "box_center"), _ptr(box_radius, torch.float64, "box_radius"),
+            nb, int(p), int(precision), int(norm), flags, _ptr(out, torch.float64, "out"),
+            ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream(stream))
+    _check(rc)
+    return out
+
+
+def tri_single(*args, **kw):
+    return run(TRI_SINGLE, *args, **kw)
+
+
+def tri_double(*args, **kw):
+    return run(TRI_DOUBLE, *args, **kw)
+
+
+def segment(*args, **kw):
+    return run(SEGMENT, *args, **kw)
+
+
+def tet(*args, **kw):
+    return run(TET, *args, **kw)
+
+
+def bucket(elem_box, n_boxes, stream=None, workspace=None):
+    """Stable grouping of elements by box: (perm [N] int32, box_start [B+1] int32, workspace)."""
+    n = int(elem_box.shape[0])
+    perm = torch.empty(max(n, 1), dtype=torch.int32, device=elem_box.device)[:n]
+    box_start = torch.empty(n_boxes + 1, dtype=torch.int32, device=elem_box.device)
+    if workspace is None:
+        nbytes = int(lib().q2x_bucket_workspace_bytes(n, n_boxes))
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=elem_box.device)
+        off = (-ws.data_ptr()) % 256
+        workspace = ws[off:off + nbytes]
+    _check(lib().q2x_bucket(_ptr(elem_box, torch.int32, "elem_box"), n, int(n_boxes),
+                            ctypes.c_void_p(perm.data_ptr()) if n else None,
+                            ctypes.c_void_p(box_start.data_ptr()), ctypes.c_void_p(workspace.data_ptr()),
+                            workspace.numel(), _stream(stream)))
+    return perm, box_start, workspace
+
+
+def status(workspace, stream=None):
+    """(flags, n_degenerate, n_skipped) of the last call that used `workspace`."""
+    f = ctypes.c_uint32(0)
+    d = ctypes.c_int64(0)
+    s = ctypes.c_int64(0)
+    _check(lib().q2x_status_get(ctypes.c_void_p(workspace.data_ptr()), _stream(stream), ctypes.byref(f),
+                                ctypes.byref(d), ctypes.byref(s)))
+    return int(f.value), int(d.value), int(s.value)
+
+
+def profile_enable(on=True):
+    lib().q2x_profile_enable(1 if on else 0)
+
+
+def profile_reset():
+    lib().q2x_profile_reset()
+
+
+def profile_read():
+    """(recursion_ms, recursion_launches, call_ms, calls) since the last reset."""
+    a = ctypes.c_double(0)
+    b = ctypes.c_int64(0)
+    c = ctypes.c_double(0)
+    d = ctypes.c_int64(0)
+    _check(lib().q2x_profile_read(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)))
+    return a.value, int(b.value), c.value, int(d.value)
+
+
+def version():
+    return lib().q2x_version().decode()
+
+
+def job_tensors(job, device="cuda"):
+    """Device tensors of a q2x_inputs Job (verts, elems, density, elem_box, box_center, box_radius)."""
+    t = lambda a, dt: torch.as_tensor(a, dtype=dt).contiguous().to(device)  # noqa: E731
+    return (t(job.verts, torch.float64), t(job.elems, torch.int32), t(job.density, torch.float64),
+            t(job.elem_box, torch.int32), t(job.box_center, torch.float64), t(job.box_radius, torch.float64))

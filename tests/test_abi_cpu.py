@@ -1,0 +1,75 @@
+"""The C-ABI library loads and exports every symbol include/q2x.h declares;
+host-side argument validation (no GPU work is issued by these calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "q2x.h")
+
+
+def _ensure_built():
+    from paper_2107_10942_amd import build
+    if not os.path.exists(build.LIB):
+        build.build(force=False)
+    return build.LIB
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(q2x_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for n in ("q2x_tri_single", "q2x_tri_double", "q2x_segment", "q2x_tet", "q2x_workspace_bytes",
+              "q2x_status_get", "q2x_bucket"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(_ensure_built())
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+    from paper_2107_10942_amd import q2x
+    assert set(q2x.EXPORTS) == set(declared_functions())
+
+
+def test_workspace_bytes_and_argument_errors():
+    _ensure_built()
+    from paper_2107_10942_amd import q2x
+    L = q2x.lib()
+    assert q2x.workspace_bytes(q2x.TRI_SINGLE, 1000, 100, 16) > 0
+    assert q2x.workspace_bytes(q2x.TRI_SINGLE, 1000, 100, q2x.P_MAX + 1) == 0
+    assert q2x.workspace_bytes(7, 1000, 100, 8) == 0
+    assert q2x.workspace_bytes(q2x.TET, -1, 100, 8) == 0
+    # larger p and more elements never need less workspace
+    assert q2x.workspace_bytes(q2x.TET, 5000, 100, 20) >= q2x.workspace_bytes(q2x.TET, 1000, 100, 8)
+    vp = ctypes.c_void_p
+    # p out of range -> synchronous error, before any device work
+    rc = L.q2x_tri_single(None, 0, None, 0, None, None, None, None, 0, 99, 0, 0, 0, None, vp(256), 1 << 20, None)
+    assert rc == -2
+    # null workspace
+    rc = L.q2x_tri_single(None, 0, None, 0, None, None, None, None, 0, 8, 0, 0, 0, None, None, 0, None)
+    assert rc == -3
+    # misaligned workspace
+    rc = L.q2x_tet(None, 0, None, 0, None, None, None, None, 0, 8, 0, 0, 0, None, vp(260), 1 << 20, None)
+    assert rc == -3
+    # unknown precision / norm / flag bits
+    rc = L.q2x_segment(None, 0, None, 0, None, None, None, None, 0, 8, 5, 0, 0, None, vp(256), 1 << 20, None)
+    assert rc == -1
+    rc = L.q2x_segment(None, 0, None, 0, None, None, None, None, 0, 8, 0, 3, 0, None, vp(256), 1 << 20, None)
+    assert rc == -1
+    rc = L.q2x_segment(None, 0, None, 0, None, None, None, None, 0, 8, 0, 0, 64, None, vp(256), 1 << 20, None)
+    assert rc == -1
+    # elements without arrays
+    rc = L.q2x_tri_double(None, 3, None, 10, None, None, None, None, 0, 8, 0, 0, 0, None, vp(256), 1 << 20, None)
+    assert rc == -1
+    # workspace too small
+    rc = L.q2x_tri_single(vp(8), 3, vp(4), 1, vp(8), vp(4), vp(8), vp(8), 1, 8, 0, 0, 0, vp(8), vp(256), 16, None)
+    assert rc == -3
+    assert L.q2x_status_string(-2).startswith(b"Q2X_ERR_P_RANGE")
+    assert b"gfx950" in L.q2x_version()

@@ -1,0 +1,225 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bar: scale-aware per-(box, degree) error <= 1e-12 for the plain FP64 kernel
+and <= 1e-5 for the FP32-mixed kernel; integer/index work bit-exact.
+"""
+import numpy as np
+import pytest
+
+import metrics
+from gpu_util import (FP32_MIXED, FP64, TOL, oracle_ref, run_gpu, sample_boxes, scale, small_job, sub_job)
+
+pytestmark = pytest.mark.gpu
+
+KINDS = [0, 1, 2, 3]
+KNAME = {0: "tri_single", 1: "tri_double", 2: "segment", 3: "tet"}
+
+
+def _check(F, R, A, p, prec, label=""):
+    err = metrics.scale_aware_error(F, R, A, p)
+    worst = float(np.max(err)) if err.size else 0.0
+    print(f"{label} scale-aware max {worst:.3e}", flush=True)
+    assert np.all(np.isfinite(F))
+    assert worst <= TOL[prec], (label, worst)
+    return worst
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32_MIXED])
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("p", [0, 1, 3, 4, 7, 9, 13, 16, 20, 24, 32])
+def test_small_parity(kind, prec, p):
+    """Ragged N (not a multiple of 64), one box cut by several tile edges,
+    empty boxes, every order bucket and orders between buckets."""
+    job = small_job(kind, 517, 40, p, seed=kind * 100 + p)
+    F, st = run_gpu(job, prec)
+    R = oracle_ref(job)
+    A = scale(job)
+    _check(F, R, A, p, prec, f"{KNAME[kind]} p={p} prec={prec}")
+    assert st[0] == 0 and st[2] == 0
+    # empty boxes are exactly zero
+    empty = np.nonzero(job.boxes.counts == 0)[0]
+    assert np.all(F[empty] == 0)
+    if kind == 1:
+        assert np.all(F[:, 0] == 0)  # the double layer has no monopole
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32_MIXED])
+def test_config_icosphere3_full(prec):
+    """1,280-triangle unit icosphere, level 3, p = 8, single layer: all boxes."""
+    from q2x_inputs import configs
+    job = configs.sphere_small()
+    F, st = run_gpu(job, prec)
+    R = oracle_ref(job)
+    _check(F, R, scale(job), job.p, prec, f"icosphere3 prec={prec}")
+    assert st == (0, 0, 0)
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32_MIXED])
+@pytest.mark.parametrize("layer", ["single", "double"])
+def test_config_perturbed_sphere_sampled(prec, layer):
+    """81,920-triangle perturbed sphere, level 5, p = 16 at full size in the
+    launch configuration the benchmark times; oracle on a box sample."""
+    from q2x_inputs import configs
+    a, b = configs.perturbed_sphere_pair()
+    job = a if layer == "single" else b
+    F, st = run_gpu(job, prec)
+    boxes = sample_boxes(job, 120, seed=3)
+    sj = sub_job(job, boxes)
+    R = oracle_ref(sj, boxes=boxes)
+    A = scale(sj, boxes=boxes)
+    _check(F[boxes], R, A, job.p, prec, f"perturbed {layer} prec={prec}")
+    assert st == (0, 0, 0)
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32_MIXED])
+@pytest.mark.parametrize("which", ["tets", "segments"])
+def test_config_volume_filaments_sampled(prec, which):
+    """511,104 Kuhn tetrahedra and 1,000,000 random-walk segments, level 6,
+    p = 12 at full size; oracle on a box sample (with the fullest box)."""
+    from q2x_inputs import configs
+    job = configs.kuhn_tet_volume() if which == "tets" else configs.random_filaments()
+    F, st = run_gpu(job, prec)
+    boxes = sample_boxes(job, 60 if which == "tets" else 25, seed=4)
+    sj = sub_job(job, boxes)
+    R = oracle_ref(sj, boxes=boxes)
+    A = scale(sj, boxes=boxes)
+    _check(F[boxes], R, A, job.p, prec, f"{which} prec={prec}")
+    assert st == (0, 0, 0)
+
+
+def test_bucket_bit_exact():
+    import torch
+
+    import oracle
+    from paper_2107_10942_amd import q2x
+    rng = np.random.default_rng(7)
+    for n, nb in [(0, 5), (1, 1), (63, 3), (1000, 37), (5000, 300), (70000, 70000), (200000, 4400)]:
+        eb = rng.integers(-3, nb + 3, size=n).astype(np.int32) if n else np.zeros(0, np.int32)
+        perm, bs, ws = q2x.bucket(torch.as_tensor(eb).cuda(), nb)
+        f, _, skipped = q2x.status(ws)
+        torch.cuda.synchronize()
+        rp, rbs, bad = oracle.bucket(eb, nb)
+        assert np.array_equal(bs.cpu().numpy().astype(np.int64), rbs), (n, nb)
+        pv = perm.cpu().numpy()
+        assert np.array_equal(pv[: len(rp)], rp), (n, nb)
+        # the invalid elements follow, in element order
+        inval = np.nonzero((eb < 0) | (eb >= nb))[0]
+        assert np.array_equal(pv[len(rp):], inval)
+        assert skipped == bad and (bool(f & q2x.FLAG_BAD_BOX) == (bad > 0))
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32_MIXED])
+def test_presorted_and_repeat_are_bitwise_identical(prec):
+    job = small_job(0, 900, 30, 12, seed=11)
+    F1, _ = run_gpu(job, prec)
+    F2, _ = run_gpu(job, prec)
+    assert np.array_equal(F1, F2)
+    order = np.argsort(job.elem_box, kind="stable")
+    from q2x_inputs import configs, octree
+    bx = octree.Boxes(level=0, lo=-1, half=1, h=0.25, elem_box=job.elem_box[order], center=job.box_center,
+                      radius=job.box_radius, morton=job.boxes.morton, counts=job.boxes.counts)
+    js = configs.Job(name="sorted", kind=0, p=12, verts=job.verts, elems=job.elems[order], density=job.density[order],
+                     boxes=bx)
+    F3, st = run_gpu(js, prec, presorted=True)
+    assert st[0] == 0
+    assert np.array_equal(F1, F3)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_moment_normalisation(kind):
+    job = small_job(kind, 300, 12, 9, seed=21)
+    F, _ = run_gpu(job, FP64, norm=1)
+    R = oracle_ref(job, norm=1)
+    # MOMENT = (-1)^{n+m} 4pi conj(FMM): the same scale times 4pi
+    _check(F, R, 4 * np.pi * scale(job), job.p, FP64, f"moment {KNAME[kind]}")
+
+
+def test_accumulate_adds():
+    import torch
+    job = small_job(3, 400, 20, 8, seed=5)
+    F1, _ = run_gpu(job, FP64)
+    out = torch.zeros((job.n_boxes, 81, 2), dtype=torch.float64, device="cuda")
+    out[..., 0] = 1.5
+    F2, _ = run_gpu(job, FP64, accumulate=True, out=out)
+    np.testing.assert_allclose(F2, F1 + 1.5, rtol=0, atol=1e-15 * np.max(np.abs(F1)) + 1e-15)
+
+
+def test_mixed_precision_radius_invariance():
+    """The FP32-mixed result does not depend on the scaling radius beyond FP32
+    rounding; the FP64 path ignores it."""
+    job = small_job(0, 500, 20, 16, seed=8)
+    A = scale(job)
+    Fa, _ = run_gpu(job, FP32_MIXED)
+    Fb, _ = run_gpu(job, FP32_MIXED, radius=job.box_radius * 3.7)
+    _check(Fa, Fb, A, 16, FP32_MIXED, "rho x3.7")
+    Fc, _ = run_gpu(job, FP64)
+    Fd, _ = run_gpu(job, FP64, radius=job.box_radius * 3.7)
+    assert np.array_equal(Fc, Fd)
+
+
+def test_status_flags_and_skips():
+    job = small_job(0, 300, 10, 6, seed=9)
+    R = oracle_ref(job)
+    A = scale(job)
+    # a degenerate triangle (repeated vertex) contributes zero and is counted
+    j2 = small_job(0, 300, 10, 6, seed=9)
+    j2.elems[5, 2] = j2.elems[5, 1]
+    F, st = run_gpu(j2, FP64)
+    assert st[0] == 0 and st[1] == 1 and st[2] == 0
+    Rd = oracle_ref(j2)
+    _check(F, Rd, A, 6, FP64, "degenerate")
+    # bad box ids and a NaN vertex are skipped and flagged
+    j3 = small_job(0, 300, 10, 6, seed=9)
+    j3.boxes.elem_box = j3.elem_box.copy()
+    j3.boxes.elem_box[[3, 4]] = [-1, 10]
+    j3.verts[j3.elems[7, 0]] = np.nan
+    F, st = run_gpu(j3, FP64)
+    from paper_2107_10942_amd import q2x
+    assert st[0] & q2x.FLAG_BAD_BOX and st[0] & q2x.FLAG_NONFINITE
+    assert st[2] == 3
+    keep = np.ones(300, bool)
+    keep[[3, 4, 7]] = False
+    from q2x_inputs import configs, octree
+    bx = octree.Boxes(level=0, lo=-1, half=1, h=0.25, elem_box=job.elem_box[keep], center=job.box_center,
+                      radius=job.box_radius, morton=job.boxes.morton, counts=None)
+    jk = configs.Job(name="k", kind=0, p=6, verts=job.verts, elems=job.elems[keep], density=job.density[keep], boxes=bx)
+    _check(F, oracle_ref(jk), A, 6, FP64, "skipped")
+    # a bad radius only matters to the scaled (mixed) path
+    F, st = run_gpu(job, FP32_MIXED, radius=np.where(np.arange(10) == 4, -1.0, job.box_radius))
+    assert st[0] & q2x.FLAG_BAD_RADIUS
+    assert np.all(F[4] == 0)
+    # presorted flag on unsorted ids is reported
+    F, st = run_gpu(job, FP64, presorted=True)
+    assert st[0] & q2x.FLAG_NOT_SORTED
+
+
+def test_empty_inputs():
+    import torch
+    from paper_2107_10942_amd import q2x
+    job = small_job(0, 10, 5, 4, seed=1)
+    v, e, d, eb, bc, br = q2x.job_tensors(job)
+    out = torch.full((5, 25, 2), 7.0, dtype=torch.float64, device="cuda")
+    q2x.tri_single(v, e[:0], d[:0], eb[:0], bc, br, 4, out=out)
+    torch.cuda.synchronize()
+    assert torch.all(out == 0)
+    out0 = torch.empty((0, 25, 2), dtype=torch.float64, device="cuda")
+    q2x.tri_single(v, e, d, eb, bc[:0], br[:0], 4, out=out0)  # every id is out of range
+    torch.cuda.synchronize()
+
+
+def test_closed_surface_double_layer_on_gpu():
+    """Constant unit density over a closed surface in one box: all double-layer
+    moments vanish (flux of grad R_n^m), to rounding of the summed terms."""
+    from q2x_inputs import meshes, octree, configs
+    v, f = meshes.icosphere(3)
+    v = v * 0.1
+    n = f.shape[0]
+    bx = octree.Boxes(level=0, lo=-1, half=1, h=0.25, elem_box=np.zeros(n, np.int32),
+                      center=np.array([[0.01, -0.02, 0.03]]), radius=np.array([0.2]), morton=np.zeros(1),
+                      counts=np.array([n]))
+    job = configs.Job(name="closed", kind=1, p=12, verts=v, elems=f, density=np.ones(n), boxes=bx)
+    A = scale(job)
+    for prec in (FP64, FP32_MIXED):
+        F, _ = run_gpu(job, prec)
+        err = metrics.scale_aware_error(F, np.zeros_like(F), A, 12)
+        assert np.max(err) <= TOL[prec]
