@@ -175,15 +175,15 @@ const char* q2x_status_string(int status);
 
 /*
  * Kernel timing for measurement.  When enabled, each call records HIP events
- * around its recursion kernel on the call's stream; q2x_profile_read
- * synchronises those events and returns the summed duration (ms) and the
- * launch count since the last reset, for the recursion kernel and for the
- * whole call (bucketing included).
+ * on its own stream around its recursion kernel and around the whole call;
+ * q2x_profile_read synchronises those events and returns, per element kind
+ * (arrays of 4 indexed by q2x_kind), the summed recursion-kernel time (ms),
+ * the summed whole-call time (ms, bucketing and fix-up included) and the
+ * number of calls since the last reset.  Any output pointer may be NULL.
  */
 void q2x_profile_enable(int on);
 void q2x_profile_reset(void);
-q2x_status q2x_profile_read(double* recursion_ms, int64_t* recursion_launches, double* call_ms,
-                            int64_t* calls);
+q2x_status q2x_profile_read(double* recursion_ms, double* call_ms, int64_t* calls);
 
 /* Library version string. */
 const char* q2x_version(void);

@@ -95,8 +95,8 @@ struct Prof {
   std::mutex mu;
   bool on = false;
   struct Ev {
-    hipEvent_t a, b, c;  // call start, recursion start, recursion end (call end = c after fixup? no: d)
-    hipEvent_t d;
+    hipEvent_t a, b, c, d;  // call start, recursion start, recursion end, call end
+    int kind;
   };
   std::vector<Ev> evs;
   std::vector<Ev> pool;
@@ -218,6 +218,7 @@ q2x_status run(int kind, const double* verts, int64_t n_verts, const int32_t* el
   }
   if (timing) {
     hipEventRecord(ev.d, s);
+    ev.kind = kind;
     std::lock_guard<std::mutex> g(PR.mu);
     PR.evs.push_back(ev);
   }
@@ -316,22 +317,25 @@ void q2x_profile_reset(void) {
   P.evs.clear();
 }
 
-q2x_status q2x_profile_read(double* recursion_ms, int64_t* recursion_launches, double* call_ms, int64_t* calls) {
+q2x_status q2x_profile_read(double* recursion_ms, double* call_ms, int64_t* calls) {
   Prof& P = prof();
   std::lock_guard<std::mutex> g(P.mu);
-  double rec = 0.0, tot = 0.0;
+  double rec[4] = {0, 0, 0, 0}, tot[4] = {0, 0, 0, 0};
+  int64_t cnt[4] = {0, 0, 0, 0};
   for (auto& e : P.evs) {
     if (hipEventSynchronize(e.d) != hipSuccess) return Q2X_ERR_HIP;
     float a = 0.f, b = 0.f;
     if (hipEventElapsedTime(&a, e.b, e.c) != hipSuccess) return Q2X_ERR_HIP;
     if (hipEventElapsedTime(&b, e.a, e.d) != hipSuccess) return Q2X_ERR_HIP;
-    rec += a;
-    tot += b;
+    rec[e.kind] += a;
+    tot[e.kind] += b;
+    cnt[e.kind] += 1;
   }
-  if (recursion_ms) *recursion_ms = rec;
-  if (recursion_launches) *recursion_launches = (int64_t)P.evs.size();
-  if (call_ms) *call_ms = tot;
-  if (calls) *calls = (int64_t)P.evs.size();
+  for (int k = 0; k < 4; ++k) {
+    if (recursion_ms) recursion_ms[k] = rec[k];
+    if (call_ms) call_ms[k] = tot[k];
+    if (calls) calls[k] = cnt[k];
+  }
   return Q2X_OK;
 }
 

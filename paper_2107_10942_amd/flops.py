@@ -1,0 +1,95 @@
+"""Algorithmic work model of the Q2X tile kernel (per element, order p).
+
+FLOPs are counted operation by operation as the recursion of Sec. 3.4,
+Eqs. (50)-(56), is evaluated in the m >= 0 form with zero padding pruned
+(entries with m > n are never touched), one FMA = 2 FLOPs:
+
+  ladder step to degree n (one array): 3 multiplies to pre-scale xi, z by
+  1/(n+k); order 0: 1 multiply + 2 doubling adds + 2 FMAs; orders m >= 1:
+  the -xi F^{m-1} + eta F^{m+1} pair costs 10 FLOPs when F^{m+1} exists and
+  6 when it does not, the -z F^m term 4 FLOPs when F^m exists, and the
+  source term (j, i, b, a, p recursions) 4 FLOPs (2 at m = 0).
+  Per degree:  triangle single = q + j(+q) + i(+j);  segment = q + p(+q);
+  tetrahedron = q + j + b + a;  double layer = one D_nu step on i_{n-1}
+  (no pre-scale, no source) plus the q, j, i steps to degree n-1.
+  Weighting: 2 multiplies per staged tilde coefficient; reduction: 2 FP64
+  adds per element-coefficient.  Geometry (~60 FLOPs) is counted once.
+
+Bytes (algorithmic, per launch): inputs read once (per element: k vertex
+indices, density, box id, and k vertices of 24 B counted per element) plus the
+box coefficients written, B_occ (p+1)^2 16 B.
+"""
+from __future__ import annotations
+
+TRI_SINGLE, TRI_DOUBLE, SEGMENT, TET = 0, 1, 2, 3
+NV = {TRI_SINGLE: 3, TRI_DOUBLE: 3, SEGMENT: 2, TET: 4}
+GEOMETRY_FLOPS = 60
+
+
+def ladder_flops(n: int, add: bool, prescale: bool = True) -> int:
+    f = 3 if prescale else 0
+    # m = 0
+    f += 1
+    if n - 1 >= 1:
+        f += 2 + 4
+    if add:
+        f += 2
+    for m in range(1, n + 1):
+        f += 10 if m + 1 <= n - 1 else 6
+        if m <= n - 1:
+            f += 4
+        if add:
+            f += 4
+    return f
+
+
+def recursion_flops(kind: int, p: int) -> int:
+    f = 0
+    if kind == TRI_SINGLE:
+        for n in range(1, p + 1):
+            f += ladder_flops(n, False) + 2 * ladder_flops(n, True)
+    elif kind == SEGMENT:
+        for n in range(1, p + 1):
+            f += ladder_flops(n, False) + ladder_flops(n, True)
+    elif kind == TET:
+        for n in range(1, p + 1):
+            f += ladder_flops(n, False) + 3 * ladder_flops(n, True)
+    elif kind == TRI_DOUBLE:
+        for n in range(1, p + 1):
+            f += ladder_flops(n, False, prescale=False)  # l_n = D_nu i_{n-1}
+            if n < p:
+                f += ladder_flops(n, False) + 2 * ladder_flops(n, True)
+    else:
+        raise ValueError(kind)
+    return f
+
+
+def element_flops(kind: int, p: int) -> int:
+    """Total FLOPs per element: geometry + recursion + weighting + reduction."""
+    nct = (p + 1) * (p + 2) // 2
+    return GEOMETRY_FLOPS + recursion_flops(kind, p) + 2 * nct + 2 * nct
+
+
+def launch_flops(kind: int, p: int, n_elems: int) -> int:
+    return element_flops(kind, p) * n_elems
+
+
+def launch_bytes(kind: int, p: int, n_elems: int, n_boxes_occupied: int) -> int:
+    per_elem = 4 * NV[kind] + 8 + 4 + 4 + 24 * NV[kind]  # indices, density, box id, perm, vertices
+    return per_elem * n_elems + 16 * (p + 1) ** 2 * n_boxes_occupied
+
+
+# MI355X vector-ALU peak.  256 CUs x 4 SIMDs x 16 lanes = 4096 FMA lanes per
+# clock at 2.4 GHz.  FP64 FMA issues at full rate: 4096 x 2 x 2.4e9 = 78.6
+# TFLOP/s.  Non-packed FP32 FMA issues at the same rate (78.6); the 157.3
+# TFLOP/s FP32 figure needs packed (two-wide) FP32 instructions, which this
+# library is built without.
+CUS, LANES_PER_CU, CLOCK_HZ = 256, 64, 2.4e9
+PEAK_VALU_TFLOPS = CUS * LANES_PER_CU * 2 * CLOCK_HZ / 1e12  # 78.64
+PEAK_FP32_PACKED_TFLOPS = 2 * PEAK_VALU_TFLOPS                # 157.3 (not reachable here)
+PEAK_HBM_GBS = 8000.0
+
+
+if __name__ == "__main__":
+    for k, name in ((0, "tri_single"), (1, "tri_double"), (2, "segment"), (3, "tet")):
+        print(name, [recursion_flops(k, p) for p in (8, 12, 16, 20, 24)], [element_flops(k, p) for p in (8, 12, 16, 20, 24)])

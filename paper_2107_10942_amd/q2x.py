@@ -61,8 +61,8 @@ def lib():
         L.q2x_profile_enable.restype = None
         L.q2x_profile_reset.argtypes = []
         L.q2x_profile_reset.restype = None
-        L.q2x_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
-                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+        L.q2x_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_int64)]
         L.q2x_profile_read.restype = ci
         L.q2x_version.restype = ctypes.c_char_p
         _lib = L
@@ -182,13 +182,12 @@ def profile_reset():
 
 
 def profile_read():
-    """(recursion_ms, recursion_launches, call_ms, calls) since the last reset."""
-    a = ctypes.c_double(0)
-    b = ctypes.c_int64(0)
-    c = ctypes.c_double(0)
-    d = ctypes.c_int64(0)
-    _check(lib().q2x_profile_read(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)))
-    return a.value, int(b.value), c.value, int(d.value)
+    """Per kind (index = kind): (recursion_ms[4], call_ms[4], calls[4]) since the last reset."""
+    a = (ctypes.c_double * 4)()
+    c = (ctypes.c_double * 4)()
+    d = (ctypes.c_int64 * 4)()
+    _check(lib().q2x_profile_read(a, c, d))
+    return list(a), list(c), list(d)
 
 
 def version():
