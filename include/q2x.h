@@ -35,12 +35,14 @@
  *    element index inside a box) unless Q2X_PRESORTED says elem_box is
  *    already non-decreasing.  An id outside [0, n_boxes) sets
  *    Q2X_FLAG_BAD_BOX and the element is skipped.
- *  - box_radius[b] > 0 is the box radius rho used by Q2X_FP32_MIXED to scale
- *    coordinates (y - c)/rho before the FP32 recursion; the FP64 result does not
- *    depend on it.  rho <= 0 or non-finite sets Q2X_FLAG_BAD_RADIUS and the
- *    box's elements are skipped (mixed precision only).
+ *  - Precision: Q2X_FP64 runs the recursion in FP64 on y - c.  Q2X_FP32_MIXED
+ *    runs it in FP32 on (y - c)/a_e, a_e the element's largest vertex distance
+ *    from c, so the recursion works on O(1) values for any element size and
+ *    order; the geometry, the weights s_e a_e^n and the box sums stay FP64.
+ *  - box_radius is accepted for interface compatibility and is not read (the
+ *    scaling above is per element); it may be NULL.
  *  - Degenerate elements (zero length/area/volume) contribute exactly zero and
- *    are counted.  Elements with non-finite coordinates or density set
+ *    are counted.  Elements with non-finite coordinates, density or box centre set
  *    Q2X_FLAG_NONFINITE and are skipped; vertex indices outside [0, n_verts)
  *    set Q2X_FLAG_BAD_VERTEX and are skipped.  Nothing is ever written out of
  *    bounds.
@@ -81,7 +83,7 @@ enum {
 enum {
   Q2X_FLAG_BAD_BOX = 1u,
   Q2X_FLAG_NONFINITE = 2u,
-  Q2X_FLAG_BAD_RADIUS = 4u,
+  Q2X_FLAG_RESERVED = 4u, /* not set by this implementation */
   Q2X_FLAG_BAD_VERTEX = 8u,
   Q2X_FLAG_NOT_SORTED = 16u /* Q2X_PRESORTED given but elem_box decreases */
 };
@@ -99,7 +101,7 @@ size_t q2x_workspace_bytes(int kind, int64_t n_elems, int64_t n_boxes, int p, in
  *   tris    [n_tris][3] int32       vertex indices (x1, x2, x3)
  *   density [n_tris] double         sigma_e
  *   elem_box[n_tris] int32          owning leaf box of each triangle
- *   box_center [n_boxes][3] double, box_radius [n_boxes] double
+ *   box_center [n_boxes][3] double; box_radius unused (may be NULL)
  */
 q2x_status q2x_tri_single(const double* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
                           const double* density, const int32_t* elem_box, const double* box_center,

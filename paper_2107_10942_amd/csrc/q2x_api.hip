@@ -39,8 +39,6 @@ __global__ __launch_bounds__(256) void q2x_fixup_kernel(FixupArgs f) {
     }
     const int64_t t0 = s / kTile, t1 = (t - 1) / kTile;
     if (t0 == t1) continue;  // finished by the tile kernel
-    double rho = 1.0;
-    if (f.scaled) rho = f.box_radius[b];
     for (int g = lane; g < nct_out; g += 64) {
       double ar = 0.0, ai = 0.0;
       for (int64_t tt = t0; tt <= t1; ++tt) {
@@ -51,8 +49,7 @@ __global__ __launch_bounds__(256) void q2x_fixup_kernel(FixupArgs f) {
       }
       int n, m;
       tri_nm(g, n, m);
-      const double rk = f.scaled ? ipow_d(rho, n - f.double_layer) : 1.0;
-      finalize_store(row, n, m, ar, ai, rk, f.norm, f.accumulate);
+      finalize_store(row, n, m, ar, ai, f.norm, f.accumulate);
     }
   }
 }
@@ -133,10 +130,11 @@ q2x_status run(int kind, const double* verts, int64_t n_verts, const int32_t* el
   if (norm != Q2X_NORM_FMM && norm != Q2X_NORM_MOMENT) return Q2X_ERR_ARG;
   if (flags & ~(unsigned)(Q2X_ACCUMULATE | Q2X_PRESORTED)) return Q2X_ERR_ARG;
   if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return Q2X_ERR_WORKSPACE;
-  if (n_boxes > 0 && (!coeffs || !box_center || !box_radius)) return Q2X_ERR_ARG;
+  (void)box_radius;  // accepted for interface compatibility; not read (see q2x.h)
+  if (n_boxes > 0 && (!coeffs || !box_center)) return Q2X_ERR_ARG;
   if (n_elems > 0 && (!verts || !elems || !density || !elem_box)) return Q2X_ERR_ARG;
   if (((uintptr_t)coeffs % 8) || ((uintptr_t)verts % 8) || ((uintptr_t)density % 8) ||
-      ((uintptr_t)box_center % 8) || ((uintptr_t)box_radius % 8) || ((uintptr_t)elems % 4) ||
+      ((uintptr_t)box_center % 8) || ((uintptr_t)elems % 4) ||
       ((uintptr_t)elem_box % 4))
     return Q2X_ERR_ARG;
   const int P = bucket_order(p);
@@ -179,7 +177,6 @@ q2x_status run(int kind, const double* verts, int64_t n_verts, const int32_t* el
   a.keys = keys;
   a.perm = perm;
   a.box_center = box_center;
-  a.box_radius = box_radius;
   a.box_start = box_start;
   a.coeffs = coeffs;
   a.partials = partials;
@@ -200,7 +197,6 @@ q2x_status run(int kind, const double* verts, int64_t n_verts, const int32_t* el
   if (n_boxes > 0) {
     FixupArgs f;
     f.box_start = box_start;
-    f.box_radius = box_radius;
     f.partials = partials;
     f.coeffs = coeffs;
     f.n_boxes = n_boxes;
@@ -208,8 +204,6 @@ q2x_status run(int kind, const double* verts, int64_t n_verts, const int32_t* el
     f.P = P;
     f.norm = norm;
     f.accumulate = a.accumulate;
-    f.scaled = (prec == Q2X_FP32_MIXED) ? 1 : 0;
-    f.double_layer = (kind == Q2X_TRI_DOUBLE) ? 1 : 0;
     const int64_t waves = n_boxes;
     int64_t blocks = (waves + 3) / 4;
     if (blocks > 65536) blocks = 65536;

@@ -34,7 +34,6 @@ struct TileArgs {
   const int32_t* keys;       // box id of each sorted position (elem_box itself when presorted)
   const int32_t* perm;       // sorted position -> element index (nullptr: identity)
   const double* box_center;
-  const double* box_radius;
   const int32_t* box_start;  // [n_boxes + 1] start position of each box
   double* coeffs;            // [n_boxes][(p+1)^2][2]
   double* partials;          // [n_tiles][2][tri(P+1)][2] raw sums of boxes cut by tile edges
@@ -50,7 +49,6 @@ struct TileArgs {
 // Arguments of the fix-up kernel (boxes cut by tile edges, empty boxes).
 struct FixupArgs {
   const int32_t* box_start;
-  const double* box_radius;
   const double* partials;
   double* coeffs;
   int64_t n_boxes;
@@ -58,8 +56,6 @@ struct FixupArgs {
   int P;                     // bucket order the partials were laid out for
   int norm;
   int accumulate;
-  int scaled;                // 1: coordinates were divided by rho (mixed precision)
-  int double_layer;          // 1: degree n scales as rho^(n-1)
 };
 
 // Logical tile of a workgroup: the hardware deals workgroups round-robin to
@@ -72,28 +68,17 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t nblk) {
   return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
-// rho^k by binary powering (k >= 0).
-__device__ __forceinline__ double ipow_d(double rho, int k) {
-  double r = 1.0, b = rho;
-  while (k > 0) {
-    if (k & 1) r *= b;
-    b *= b;
-    k >>= 1;
-  }
-  return r;
-}
-
 // Turn the raw tilde box sum T_n^m (sum_e s_e t~_{e,n}^m, m >= 0) into the two
 // output coefficients and store (or add) them.
-//   FMM   : F_n^{m}  = (-1)^n rho^k i^{-m} conj(T),  F_n^{-m} = (-1)^n rho^k i^{-m} T
-//   MOMENT: M_n^{m}  = (-1)^m 4pi rho^k i^{m} T,     M_n^{-m} = (-1)^m 4pi rho^k i^{m} conj(T)
+//   FMM   : F_n^{m}  = (-1)^n i^{-m} conj(T),  F_n^{-m} = (-1)^n i^{-m} T
+//   MOMENT: M_n^{m}  = (-1)^m 4pi i^{m} T,     M_n^{-m} = (-1)^m 4pi i^{m} conj(T)
 // (tilde <-> plain: Sec. 3.4, Eqs. (47),(49); symmetry Eq. (12); weights Eq. (20)).
-__device__ __forceinline__ void finalize_store(double* row, int n, int m, double tr, double ti, double rho_k,
-                                               int norm, int accumulate) {
+__device__ __forceinline__ void finalize_store(double* row, int n, int m, double tr, double ti, int norm,
+                                               int accumulate) {
   double a, b;  // value for +m
   double c, d;  // value for -m
   if (norm == Q2X_NORM_FMM) {
-    const double base = ((n & 1) ? -rho_k : rho_k);
+    const double base = (n & 1) ? -1.0 : 1.0;
     // i^{-m}: m%4 = 0 -> 1, 1 -> -i, 2 -> -1, 3 -> i
     const double xr = base * tr, xi = base * ti;  // base * T
     double pr, pi;                                 // i^{-m} * (base*T)
@@ -113,7 +98,7 @@ __device__ __forceinline__ void finalize_store(double* row, int n, int m, double
     }
     a = qr; b = qi; c = pr; d = pi;
   } else {
-    const double base = ((m & 1) ? -k4Pi : k4Pi) * rho_k;
+    const double base = (m & 1) ? -k4Pi : k4Pi;
     const double xr = base * tr, xi = base * ti;
     double pr, pi;  // i^{m} * (base*T)
     switch (m & 3) {

@@ -4,14 +4,18 @@
 // Per lane: FP64 geometry of its element relative to its box centre, then the
 // m >= 0 ("tilde") recursions of Sec. 3.4, Eqs. (50)-(55), degree by degree,
 // with the whole recursion state in VGPRs (template order P, fully unrolled).
-// Every degree's weighted outputs s_e t~_n^m go to an LDS stage; when a group
-// of degrees ("chunk", <= CMAX coefficients) is complete the wavefront
+// The FP32 path runs the recursion on Y = (x - c)/a_e, a_e the element's
+// largest vertex distance from c, so every value is O(1/(n+m)!) whatever the
+// element's size and position (degree n of the result scales as a_e^n); the
+// FP64 path runs on x - c unscaled.
+// Every degree's outputs t~_n^m go to an LDS stage, and the FP64 factor
+// s_e a_e^n (s_e = sigma_e J_e / 4pi) to a small table beside it.  When a
+// group of degrees ("chunk", <= CMAX coefficients) is complete the wavefront
 // transposes through LDS -- lane = coefficient -- and walks the 64 elements in
-// order, summing in FP64 and flushing at every box boundary (boxes are
-// contiguous because elements are sorted by box).  Boxes wholly inside the tile
-// are finalised and stored directly; a box cut by a tile edge leaves a raw
-// partial sum for the fix-up kernel.  The order of every sum is fixed by the
-// element order, so results are bitwise reproducible.
+// order, one box segment at a time, summing factor * value in FP64.  Boxes
+// wholly inside the tile are finalised and stored directly; a box cut by a
+// tile edge leaves a raw partial sum for the fix-up kernel.  The order of every
+// sum is fixed by the element order, so results are bitwise reproducible.
 #pragma once
 
 #include "q2x_internal.hpp"
@@ -61,7 +65,6 @@ template <int N, bool ADD, typename T, int P1>
 __device__ __forceinline__ void ladder(CArr<T, P1>& out, const CArr<T, P1>& F, const CArr<T, P1>& add, T sxr,
                                        T sxi, T sz, T inv) {
   static_assert(N >= 1 && N < P1, "degree out of range");
-  // m = 0
   {
     T v = -sz * F.r[0];
     if constexpr (N - 1 >= 1) {
@@ -74,7 +77,6 @@ __device__ __forceinline__ void ladder(CArr<T, P1>& out, const CArr<T, P1>& F, c
   }
   static_for<1, N + 1>([&](auto MM) {
     constexpr int m = decltype(MM)::value;
-    // Am = F^{m-1}; Ap = F^{m+1} (if m+1 <= N-1); C = F^m (if m <= N-1)
     const T amr = F.r[m - 1];
     const T ami = (m - 1 == 0) ? T(0) : F.i[m - 1];
     T re, im;
@@ -117,43 +119,44 @@ struct ChunkPlan {
     while (!is_end(e)) ++e;
     return e;
   }
+  static constexpr int max_degrees() {
+    int mx = 0;
+    for (int n = 0; n <= P; ++n) {
+      const int d = n - first_level(n) + 1;
+      if (d > mx) mx = d;
+    }
+    return mx;
+  }
 };
-
-__device__ __forceinline__ double readlane_d(double v, int l) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
 
 template <int KIND>
 struct KindInfo;
 template <>
 struct KindInfo<Q2X_TRI_SINGLE> {
   static constexpr int nv = 3;
-  static constexpr int rho_shift = 0;
+  static constexpr int shift = 0;
 };
 template <>
 struct KindInfo<Q2X_TRI_DOUBLE> {
   static constexpr int nv = 3;
-  static constexpr int rho_shift = 1;
+  static constexpr int shift = 1;  // degree n is built from i_{n-1}: scales as a^(n-1)
 };
 template <>
 struct KindInfo<Q2X_SEGMENT> {
   static constexpr int nv = 2;
-  static constexpr int rho_shift = 0;
+  static constexpr int shift = 0;
 };
 template <>
 struct KindInfo<Q2X_TET> {
   static constexpr int nv = 4;
-  static constexpr int rho_shift = 0;
+  static constexpr int shift = 0;
 };
 
 template <typename T>
 struct PrecInfo;
 template <>
 struct PrecInfo<float> {
-  static constexpr bool scaled = true;  // FP32 recursion on (y - c)/rho
+  static constexpr bool scaled = true;  // FP32 recursion on (y - c)/a_e
   static constexpr int cmax = 64;
 };
 template <>
@@ -167,13 +170,16 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
   using C2 = typename Cx2<T>::type;
   constexpr int P1 = P + 1;
   constexpr int NV = KindInfo<KIND>::nv;
+  constexpr int SHIFT = KindInfo<KIND>::shift;
   constexpr int CMAX = (PrecInfo<T>::cmax > P + 1) ? PrecInfo<T>::cmax : P + 1;
-  constexpr int SSTR = kTile + 1;  // padded stride of one coefficient row in the stage
+  constexpr int SSTR = kTile + 1;  // padded row stride (elements) of the stage and factor tables
   constexpr int NCT = tri(P + 1);
   constexpr bool SCALED = PrecInfo<T>::scaled;
   using Plan = ChunkPlan<P, CMAX>;
+  constexpr int DMAX = Plan::max_degrees();
 
   __shared__ C2 stage[CMAX * SSTR];
+  __shared__ double fac[DMAX * SSTR];
 
   const int64_t tile = xcd_tile(blockIdx.x, n_tiles);
   const int lane = threadIdx.x;
@@ -185,15 +191,15 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
   const bool in_range = lane < ne;
 
   // ---- element, box and FP64 geometry (Sec. 3.1, Eqs. (8)-(9); Sec. 3.3, Eq. (21))
-  int key = in_range ? a.keys[q] : INT32_MIN;
-  const bool box_ok = in_range && key >= 0 && key < a.n_boxes;
-  int64_t e = in_range ? (a.perm ? (int64_t)a.perm[q] : q) : 0;
+  const int key = in_range ? a.keys[q] : INT32_MIN;
+  const bool box_ok = in_range && key >= 0 && key < a.n_boxes;  // (bad ids were counted by the bucketing)
+  const int64_t e = in_range ? (a.perm ? (int64_t)a.perm[q] : q) : 0;
   uint32_t flag = 0;
   bool ok = box_ok;
   double xv[NV][3];
+#pragma unroll
   for (int k = 0; k < NV; ++k) xv[k][0] = xv[k][1] = xv[k][2] = 0.0;
-  double sigma = 0.0, cx = 0.0, cy = 0.0, cz = 0.0, rho = 1.0;
-  // (ids outside [0, B) were counted by the bucketing step)
+  double sigma = 0.0, cx = 0.0, cy = 0.0, cz = 0.0;
   if (ok) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
@@ -211,16 +217,7 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
     cx = a.box_center[3 * (int64_t)key];
     cy = a.box_center[3 * (int64_t)key + 1];
     cz = a.box_center[3 * (int64_t)key + 2];
-    if constexpr (SCALED) {
-      rho = a.box_radius[key];
-      if (!(rho > 0.0) || !isfinite(rho)) {
-        ok = false;
-        flag |= Q2X_FLAG_BAD_RADIUS;
-      }
-    }
   }
-  // edge vectors from the absolute vertices; Jacobian (Eq. (9)) and normal
-  double J = 0.0, nx = 0.0, ny = 0.0, nz = 0.0;
   if (ok) {
     bool fin = isfinite(sigma) && isfinite(cx) && isfinite(cy) && isfinite(cz);
 #pragma unroll
@@ -230,7 +227,8 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
       flag |= Q2X_FLAG_NONFINITE;
     }
   }
-  bool degenerate = false;
+  // Jacobian (Eq. (9)) and unit normal from the absolute vertices
+  double J = 0.0, nx = 0.0, ny = 0.0, nz = 0.0;
   if (ok) {
     const double ux = xv[1][0] - xv[0][0], uy = xv[1][1] - xv[0][1], uz = xv[1][2] - xv[0][2];
     if constexpr (KIND == Q2X_SEGMENT) {
@@ -250,40 +248,45 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
         }
       }
     }
-    degenerate = !(J > 0.0);
   }
-  if (!ok) {
-    // skipped element: zero weight and zero (finite) geometry
-    J = 0.0;
-    nx = ny = nz = 0.0;
-  }
-  // weight s_e = sigma J / (4 pi) (Sec. 3.2, Eq. (20))
+  const bool degenerate = ok && !(J > 0.0);
+  // weight s_e = sigma J / (4 pi) (Sec. 3.2, Eq. (20)); skipped elements weigh 0
   const double w64 = ok ? sigma * J * kInv4Pi : 0.0;
-  const T w = (T)w64;
-  const double inv_rho = SCALED ? 1.0 / rho : 1.0;
 
-  // scaled vertex coordinates Y_k = (x_k - c)/rho  ->  xi_k = (Y_x + i Y_y)/2, z_k = Y_z
+  // element scale a_e (FP32 path) and the recursion's vertex data
+  double X[NV][3];
+  double amax2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    X[k][0] = ok ? xv[k][0] - cx : 0.0;
+    X[k][1] = ok ? xv[k][1] - cy : 0.0;
+    X[k][2] = ok ? xv[k][2] - cz : 0.0;
+    amax2 = fmax(amax2, X[k][0] * X[k][0] + X[k][1] * X[k][1] + X[k][2] * X[k][2]);
+  }
+  double scl = 1.0;
+  if constexpr (SCALED) {
+    scl = sqrt(amax2);
+    if (!(scl > 0.0)) scl = 1.0;
+  }
+  const double inv_scl = 1.0 / scl;
   T vxr[NV], vxi[NV], vz[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
-    const double X = ok ? (xv[k][0] - cx) * inv_rho : 0.0;
-    const double Y = ok ? (xv[k][1] - cy) * inv_rho : 0.0;
-    const double Z = ok ? (xv[k][2] - cz) * inv_rho : 0.0;
-    vxr[k] = (T)(0.5 * X);
-    vxi[k] = (T)(0.5 * Y);
-    vz[k] = (T)Z;
+    vxr[k] = (T)(0.5 * X[k][0] * inv_scl);
+    vxi[k] = (T)(0.5 * X[k][1] * inv_scl);
+    vz[k] = (T)(X[k][2] * inv_scl);
   }
+  // running FP64 factor s_e * a_e^(n - SHIFT) for the degree being produced
+  double fpow = (SHIFT == 1) ? w64 * inv_scl : w64;
 
-  // ---- status (one atomic per wavefront)
+  // ---- status (one atomic per wavefront and counter)
   {
     const uint64_t deg_mask = __ballot(degenerate);
     const uint64_t skip_mask = __ballot(box_ok && !ok);
-    uint32_t f = flag;
-    // OR-reduce the flags over the wave (few distinct bits: ballot each)
     uint32_t fall = 0;
 #pragma unroll
     for (int b = 0; b < 5; ++b)
-      if (__ballot((f >> b) & 1u)) fall |= (1u << b);
+      if (__ballot((flag >> b) & 1u)) fall |= (1u << b);
     if (lane == 0) {
       if (deg_mask) atomicAdd(&a.status->n_degenerate, (unsigned long long)__popcll(deg_mask));
       if (skip_mask) atomicAdd(&a.status->n_skipped, (unsigned long long)__popcll(skip_mask));
@@ -306,57 +309,69 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
     constexpr int L1 = decltype(L1c)::value;
     constexpr int CB = tri(L0);
     constexpr int C = tri(L1 + 1) - tri(L0);
-    static_assert(C <= CMAX, "chunk too large");
+    static_assert(C <= CMAX && L1 - L0 + 1 <= DMAX, "chunk too large");
     __syncthreads();
     const int c = lane;
     const bool act = c < C;
     int n = 0, m = 0;
-    tri_nm(CB + c, n, m);
+    tri_nm(CB + (act ? c : 0), n, m);
     const bool wr = act && n <= p;
-    const int kpow = n - KindInfo<KIND>::rho_shift;
-    double accr = 0.0, acci = 0.0;
-    int seg_a = 0;
-    auto flush = [&](int sa, int sb) {
+    const C2* srow = stage + (act ? c : 0) * SSTR;
+    const double* frow = fac + (n - L0) * SSTR;
+    int sa = 0;
+    while (sa < ne) {  // uniform: one box segment [sa, sb) per iteration
+      const uint64_t later = (sa + 1 < 64) ? (bnd >> (sa + 1)) : 0ull;
+      const int sb = later ? sa + 1 + __builtin_ctzll(later) : ne;
+      double accr = 0.0, acci = 0.0;
+#pragma unroll 4
+      for (int el = sa; el < sb; ++el) {
+        const C2 v = srow[el];
+        const double f = frow[el];
+        accr = __builtin_fma((double)v.x, f, accr);
+        acci = __builtin_fma((double)v.y, f, acci);
+      }
       const int box = __builtin_amdgcn_readlane(key, sa);
-      const double rb = SCALED ? readlane_d(rho, sa) : 1.0;
-      if (box < 0 || box >= a.n_boxes) return;  // skipped (invalid) elements
-      const bool open = (sa == 0 && head_open) || (sb == kTile && tail_open);
-      if (!wr) return;
-      if (open) {
-        const int slot = (sa == 0) ? 0 : 1;
-        double* pp = a.partials + ((tile * 2 + slot) * (int64_t)NCT + CB + c) * 2;
-        pp[0] = accr;
-        pp[1] = acci;
-      } else {
-        const double rk = SCALED ? ipow_d(rb, kpow) : 1.0;
-        finalize_store(a.coeffs + (int64_t)box * ncoef_out * 2, n, m, accr, acci, rk, a.norm, a.accumulate);
+      if (box >= 0 && box < a.n_boxes && wr) {
+        const bool open = (sa == 0 && head_open) || (sb == kTile && tail_open);
+        if (open) {
+          const int slot = (sa == 0) ? 0 : 1;
+          double* pp = a.partials + ((tile * 2 + slot) * (int64_t)NCT + CB + c) * 2;
+          pp[0] = accr;
+          pp[1] = acci;
+        } else {
+          finalize_store(a.coeffs + (int64_t)box * ncoef_out * 2, n, m, accr, acci, a.norm, a.accumulate);
+        }
       }
-    };
-    for (int el = 0; el < ne; ++el) {
-      if (el > 0 && ((bnd >> el) & 1ull)) {
-        flush(seg_a, el);
-        accr = 0.0;
-        acci = 0.0;
-        seg_a = el;
-      }
-      if (act) {
-        const C2 v = stage[c * SSTR + el];
-        accr += (double)v.x;
-        acci += (double)v.y;
-      }
+      sa = sb;
     }
-    flush(seg_a, ne);
     __syncthreads();
   };
 
-  auto put = [&](int idx, T re, T im) {
-    C2 v;
-    v.x = w * re;
-    v.y = w * im;
-    stage[idx * SSTR + lane] = v;
+  // stage degree N's outputs (unweighted) and its FP64 factor
+  auto put_level = [&](auto NNc, auto L0c, const CArr<T, P1>& V) {
+    constexpr int N = decltype(NNc)::value;
+    constexpr int L0 = decltype(L0c)::value;
+    static_for<0, N + 1>([&](auto MM) {
+      constexpr int m = decltype(MM)::value;
+      C2 v;
+      v.x = V.r[m];
+      v.y = V.i[m];
+      stage[(tri(N) - tri(L0) + m) * SSTR + lane] = v;
+    });
+    fac[(N - L0) * SSTR + lane] = fpow;
+    fpow *= scl;
+  };
+  auto end_level = [&](auto NNc) {
+    constexpr int N = decltype(NNc)::value;
+    constexpr int L0 = Plan::first_level(N);
+    if constexpr (Plan::is_end(N)) {
+      reduce_chunk(IC<L0>{}, IC<N>{});
+    } else if (N == p) {
+      reduce_chunk(IC<L0>{}, IC<Plan::end_of(N)>{});
+    }
   };
 
-  // ---- recursion over degrees (Sec. 3.4): outputs staged degree by degree
+  // ---- recursion over degrees (Sec. 3.4)
   if constexpr (KIND == Q2X_TRI_SINGLE || KIND == Q2X_TRI_DOUBLE) {
     CArr<T, P1> Q, Jj, I;
     Q.r[0] = T(1);
@@ -385,21 +400,18 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
               Jj = nJ;
               I = nI;
             }
-            static_for<0, N + 1>([&](auto MM) {
-              constexpr int m = decltype(MM)::value;
-              put(tri(N) - tri(L0) + m, I.r[m], I.i[m]);
-            });
+            put_level(IC<N>{}, IC<L0>{}, I);
           } else {
             // double layer: l~_N = D_nu i~_{N-1}, nu = (n_x + i n_y)/2 (Sec. 3.4, Eq. (56))
             if constexpr (N == 0) {
-              put(0, T(0), T(0));
+              CArr<T, P1> Z;
+              Z.r[0] = T(0);
+              Z.i[0] = T(0);
+              put_level(IC<0>{}, IC<L0>{}, Z);
             } else {
               CArr<T, P1> L;
               ladder<N, false>(L, I, I, hnx, hny, tnz, T(1));
-              static_for<0, N + 1>([&](auto MM) {
-                constexpr int m = decltype(MM)::value;
-                put(tri(N) - tri(L0) + m, L.r[m], L.i[m]);
-              });
+              put_level(IC<N>{}, IC<L0>{}, L);
               if constexpr (N < P) {
                 if (N < p) {
                   CArr<T, P1> nQ, nJ, nI;
@@ -414,11 +426,7 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
               }
             }
           }
-          if constexpr (Plan::is_end(N)) {
-            reduce_chunk(IC<L0>{}, IC<N>{});
-          } else if (N == p) {
-            reduce_chunk(IC<L0>{}, IC<Plan::end_of(N)>{});
-          }
+          end_level(IC<N>{});
         }
       }
     });
@@ -444,15 +452,8 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
             Q = nQ;
             Pp = nP;
           }
-          static_for<0, N + 1>([&](auto MM) {
-            constexpr int m = decltype(MM)::value;
-            put(tri(N) - tri(L0) + m, Pp.r[m], Pp.i[m]);
-          });
-          if constexpr (Plan::is_end(N)) {
-            reduce_chunk(IC<L0>{}, IC<N>{});
-          } else if (N == p) {
-            reduce_chunk(IC<L0>{}, IC<Plan::end_of(N)>{});
-          }
+          put_level(IC<N>{}, IC<L0>{}, Pp);
+          end_level(IC<N>{});
         }
       }
     });
@@ -486,15 +487,8 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
             B = nB;
             A = nA;
           }
-          static_for<0, N + 1>([&](auto MM) {
-            constexpr int m = decltype(MM)::value;
-            put(tri(N) - tri(L0) + m, A.r[m], A.i[m]);
-          });
-          if constexpr (Plan::is_end(N)) {
-            reduce_chunk(IC<L0>{}, IC<N>{});
-          } else if (N == p) {
-            reduce_chunk(IC<L0>{}, IC<Plan::end_of(N)>{});
-          }
+          put_level(IC<N>{}, IC<L0>{}, A);
+          end_level(IC<N>{});
         }
       }
     });

@@ -21,7 +21,7 @@ FP64, FP32_MIXED = 0, 1
 NORM_FMM, NORM_MOMENT = 0, 1
 ACCUMULATE, PRESORTED = 1, 2
 P_MAX = 32
-FLAG_BAD_BOX, FLAG_NONFINITE, FLAG_BAD_RADIUS, FLAG_BAD_VERTEX, FLAG_NOT_SORTED = 1, 2, 4, 8, 16
+FLAG_BAD_BOX, FLAG_NONFINITE, FLAG_RESERVED, FLAG_BAD_VERTEX, FLAG_NOT_SORTED = 1, 2, 4, 8, 16
 EXPORTS = ("q2x_workspace_bytes", "q2x_bucket_workspace_bytes", "q2x_bucket", "q2x_tri_single", "q2x_tri_double", "q2x_segment", "q2x_tet",
            "q2x_status_get", "q2x_status_string", "q2x_profile_enable", "q2x_profile_reset",
            "q2x_profile_read", "q2x_version")

@@ -144,17 +144,21 @@ def test_accumulate_adds():
     np.testing.assert_allclose(F2, F1 + 1.5, rtol=0, atol=1e-15 * np.max(np.abs(F1)) + 1e-15)
 
 
-def test_mixed_precision_radius_invariance():
-    """The FP32-mixed result does not depend on the scaling radius beyond FP32
-    rounding; the FP64 path ignores it."""
+def test_box_radius_is_not_read():
+    """Both precisions scale per element; the box radius argument is ignored
+    (any values, or NULL, give bitwise the same result)."""
+    import torch
+    from paper_2107_10942_amd import q2x
     job = small_job(0, 500, 20, 16, seed=8)
-    A = scale(job)
-    Fa, _ = run_gpu(job, FP32_MIXED)
-    Fb, _ = run_gpu(job, FP32_MIXED, radius=job.box_radius * 3.7)
-    _check(Fa, Fb, A, 16, FP32_MIXED, "rho x3.7")
-    Fc, _ = run_gpu(job, FP64)
-    Fd, _ = run_gpu(job, FP64, radius=job.box_radius * 3.7)
-    assert np.array_equal(Fc, Fd)
+    for prec in (FP64, FP32_MIXED):
+        Fa, _ = run_gpu(job, prec)
+        Fb, _ = run_gpu(job, prec, radius=-job.box_radius * 3.7)
+        assert np.array_equal(Fa, Fb)
+        v, e, d, eb, bc, br = q2x.job_tensors(job)
+        o = q2x.run(0, v, e, d, eb, bc, None, 16, precision=prec)
+        torch.cuda.synchronize()
+        oc = o.cpu().numpy()
+        assert np.array_equal(oc[..., 0] + 1j * oc[..., 1], Fa)
 
 
 def test_status_flags_and_skips():
@@ -184,10 +188,6 @@ def test_status_flags_and_skips():
                       radius=job.box_radius, morton=job.boxes.morton, counts=None)
     jk = configs.Job(name="k", kind=0, p=6, verts=job.verts, elems=job.elems[keep], density=job.density[keep], boxes=bx)
     _check(F, oracle_ref(jk), A, 6, FP64, "skipped")
-    # a bad radius only matters to the scaled (mixed) path
-    F, st = run_gpu(job, FP32_MIXED, radius=np.where(np.arange(10) == 4, -1.0, job.box_radius))
-    assert st[0] & q2x.FLAG_BAD_RADIUS
-    assert np.all(F[4] == 0)
     # presorted flag on unsorted ids is reported
     F, st = run_gpu(job, FP64, presorted=True)
     assert st[0] & q2x.FLAG_NOT_SORTED
