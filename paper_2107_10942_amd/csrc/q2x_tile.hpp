@@ -4,12 +4,14 @@
 // Per lane: FP64 geometry of its element relative to its box centre, then the
 // m >= 0 ("tilde") recursions of Sec. 3.4, Eqs. (50)-(55), degree by degree,
 // with the whole recursion state in VGPRs (template order P, fully unrolled).
-// The FP32 path runs the recursion on Y = (x - c)/a_e, a_e the element's
-// largest vertex distance from c, so every value is O(1/(n+m)!) whatever the
-// element's size and position (degree n of the result scales as a_e^n); the
-// FP64 path runs on x - c unscaled.
-// Every degree's outputs t~_n^m go to an LDS stage, and the FP64 factor
-// s_e a_e^n (s_e = sigma_e J_e / 4pi) to a small table beside it.  When a
+// The recursion carries G_n = (n+k)! t~_n (k = nesting depth), which removes
+// every division from Eqs. (50)-(55) and keeps the values O(1) at any order.
+// The FP32 path runs it on Y = (x - c)/a_e, a_e the element's largest vertex
+// distance from c, so nothing underflows whatever the element's size and
+// position (degree n of the result scales as a_e^n); the FP64 path runs on
+// x - c unscaled.
+// Every degree's outputs go to an LDS stage, and the FP64 factor
+// s_e a_e^n / (n+k)! (s_e = sigma_e J_e / 4pi) to a small table beside it.  When a
 // group of degrees ("chunk", <= CMAX coefficients) is complete the wavefront
 // transposes through LDS -- lane = coefficient -- and walks the 64 elements in
 // order, one box segment at a time, summing factor * value in FP64.  Boxes
@@ -57,21 +59,24 @@ __device__ __forceinline__ double fmaT(double a, double b, double c) { return __
 
 // One application of the ladder operator of Sec. 3.4, Eqs. (50)-(51) (tilde
 // form), producing degree N (orders 0..N) from degree N-1 (orders 0..N-1):
-//   out^0 = [2 Re(eta F^1) - z F^0 + add^0] * inv
-//   out^m = [-xi F^{m-1} + eta F^{m+1} - z F^m + add^m] * inv,   m >= 1,
+//   out^0 = 2 Re(eta F^1) - z F^0 + add^0
+//   out^m = -xi F^{m-1} + eta F^{m+1} - z F^m + add^m,   m >= 1,
 // with xi = (Y_x + i Y_y)/2, eta = conj(xi), z = Y_z and F^k = 0 for k > N-1.
-// The caller passes sxr = Re(xi)*inv, sxi = Im(xi)*inv, sz = z*inv.
+// The recursions of Eqs. (50)-(55) divide this by (n+k) at the k-th nesting
+// level; the kernel carries G_n = (n+k)! F_n instead, for which the division
+// disappears (G_n = D G_{n-1} + G^{(k-1)}_n, every start value 1), and folds
+// 1/(n+k)! into the FP64 per-degree factor.  (sxr2, sxi2) = 2 (sxr, sxi).
 template <int N, bool ADD, typename T, int P1>
 __device__ __forceinline__ void ladder(CArr<T, P1>& out, const CArr<T, P1>& F, const CArr<T, P1>& add, T sxr,
-                                       T sxi, T sz, T inv) {
+                                       T sxi, T sz, T sxr2, T sxi2) {
   static_assert(N >= 1 && N < P1, "degree out of range");
   {
     T v = -sz * F.r[0];
     if constexpr (N - 1 >= 1) {
-      v = fmaT(sxr + sxr, F.r[1], v);
-      v = fmaT(sxi + sxi, F.i[1], v);
+      v = fmaT(sxr2, F.r[1], v);
+      v = fmaT(sxi2, F.i[1], v);
     }
-    if constexpr (ADD) v = fmaT(inv, add.r[0], v);
+    if constexpr (ADD) v = v + add.r[0];
     out.r[0] = v;
     out.i[0] = T(0);
   }
@@ -86,6 +91,9 @@ __device__ __forceinline__ void ladder(CArr<T, P1>& out, const CArr<T, P1>& F, c
       re = fmaT(sxi, ami + api, re);
       im = sxr * (api - ami);
       im = fmaT(-sxi, amr + apr, im);
+    } else if constexpr (m - 1 == 0) {
+      re = -sxr * amr;
+      im = -sxi * amr;
     } else {
       re = fmaT(-sxr, amr, sxi * ami);
       im = fmaT(-sxr, ami, -sxi * amr);
@@ -95,8 +103,8 @@ __device__ __forceinline__ void ladder(CArr<T, P1>& out, const CArr<T, P1>& F, c
       im = fmaT(-sz, F.i[m], im);
     }
     if constexpr (ADD) {
-      re = fmaT(inv, add.r[m], re);
-      im = fmaT(inv, add.i[m], im);
+      re = re + add.r[m];
+      im = im + add.i[m];
     }
     out.r[m] = re;
     out.i[m] = im;
@@ -129,27 +137,34 @@ struct ChunkPlan {
   }
 };
 
+// nv: vertices; shift: degree n of the output scales as a^(n - shift);
+// depth: the output at degree n is G / (n + depth)!  (double layer: the
+// degree-n output is D_nu applied to G_i at degree n-1, i.e. divided by (n+1)!).
 template <int KIND>
 struct KindInfo;
 template <>
 struct KindInfo<Q2X_TRI_SINGLE> {
   static constexpr int nv = 3;
   static constexpr int shift = 0;
+  static constexpr int depth = 2;
 };
 template <>
 struct KindInfo<Q2X_TRI_DOUBLE> {
   static constexpr int nv = 3;
-  static constexpr int shift = 1;  // degree n is built from i_{n-1}: scales as a^(n-1)
+  static constexpr int shift = 1;
+  static constexpr int depth = 1;
 };
 template <>
 struct KindInfo<Q2X_SEGMENT> {
   static constexpr int nv = 2;
   static constexpr int shift = 0;
+  static constexpr int depth = 1;
 };
 template <>
 struct KindInfo<Q2X_TET> {
   static constexpr int nv = 4;
   static constexpr int shift = 0;
+  static constexpr int depth = 3;
 };
 
 template <typename T>
@@ -269,15 +284,19 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
     if (!(scl > 0.0)) scl = 1.0;
   }
   const double inv_scl = 1.0 / scl;
-  T vxr[NV], vxi[NV], vz[NV];
+  T vxr[NV], vxi[NV], vz[NV], vxr2[NV], vxi2[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     vxr[k] = (T)(0.5 * X[k][0] * inv_scl);
     vxi[k] = (T)(0.5 * X[k][1] * inv_scl);
     vz[k] = (T)(X[k][2] * inv_scl);
+    vxr2[k] = (T)(X[k][0] * inv_scl);
+    vxi2[k] = (T)(X[k][1] * inv_scl);
   }
-  // running FP64 factor s_e * a_e^(n - SHIFT) for the degree being produced
-  double fpow = (SHIFT == 1) ? w64 * inv_scl : w64;
+  // running FP64 factor s_e a_e^(n - SHIFT) / (n + DEPTH)! of the degree being produced
+  constexpr int DEPTH = KindInfo<KIND>::depth;
+  constexpr double inv_depth_fact = (DEPTH == 1) ? 1.0 : (DEPTH == 2) ? 0.5 : 1.0 / 6.0;
+  double fpow = ((SHIFT == 1) ? w64 * inv_scl : w64) * inv_depth_fact;
 
   // ---- status (one atomic per wavefront and counter)
   {
@@ -359,7 +378,8 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
       stage[(tri(N) - tri(L0) + m) * SSTR + lane] = v;
     });
     fac[(N - L0) * SSTR + lane] = fpow;
-    fpow *= scl;
+    constexpr double inv_next = 1.0 / (double)(N + 1 + DEPTH);
+    fpow = fpow * scl * inv_next;
   };
   auto end_level = [&](auto NNc) {
     constexpr int N = decltype(NNc)::value;
@@ -371,16 +391,19 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
     }
   };
 
-  // ---- recursion over degrees (Sec. 3.4)
+  // ---- recursion over degrees (Sec. 3.4), on G_n = (n+k)! F_n (see ladder())
+  // ladder step of array `dst` about vertex v (0-based), adding `src` when given
+#define Q2X_STEP(dst, prev, src, ADDF, v) \
+  ladder<N, ADDF>(dst, prev, src, vxr[v], vxi[v], vz[v], vxr2[v], vxi2[v])
   if constexpr (KIND == Q2X_TRI_SINGLE || KIND == Q2X_TRI_DOUBLE) {
-    CArr<T, P1> Q, Jj, I;
+    CArr<T, P1> Q, Jj, I;  // q at x2 (Eqs. (40)-(41)), j along x3->x2, i from x1 (Eqs. (50)-(53))
     Q.r[0] = T(1);
     Q.i[0] = T(0);
     Jj.r[0] = T(1);
     Jj.i[0] = T(0);
-    I.r[0] = T(0.5);
+    I.r[0] = T(1);
     I.i[0] = T(0);
-    const T hnx = (T)(0.5 * nx), hny = (T)(0.5 * ny), tnz = (T)nz;
+    const T hnx = (T)(0.5 * nx), hny = (T)(0.5 * ny), tnz = (T)nz, nx2 = (T)nx, ny2 = (T)ny;
     bool done = false;
     static_for<0, P + 1>([&](auto NN) {
       constexpr int N = decltype(NN)::value;
@@ -392,10 +415,9 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
           if constexpr (KIND == Q2X_TRI_SINGLE) {
             if constexpr (N >= 1) {
               CArr<T, P1> nQ, nJ, nI;
-              constexpr T i1 = T(1) / T(N), i2 = T(1) / T(N + 1), i3 = T(1) / T(N + 2);
-              ladder<N, false>(nQ, Q, Q, vxr[1] * i1, vxi[1] * i1, vz[1] * i1, i1);  // q at x2, Eq. (50)
-              ladder<N, true>(nJ, Jj, nQ, vxr[2] * i2, vxi[2] * i2, vz[2] * i2, i2);  // j along x3->x2, Eq. (52)
-              ladder<N, true>(nI, I, nJ, vxr[0] * i3, vxi[0] * i3, vz[0] * i3, i3);  // i from x1, Eq. (52)
+              Q2X_STEP(nQ, Q, Q, false, 1);
+              Q2X_STEP(nJ, Jj, nQ, true, 2);
+              Q2X_STEP(nI, I, nJ, true, 0);
               Q = nQ;
               Jj = nJ;
               I = nI;
@@ -410,15 +432,14 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
               put_level(IC<0>{}, IC<L0>{}, Z);
             } else {
               CArr<T, P1> L;
-              ladder<N, false>(L, I, I, hnx, hny, tnz, T(1));
+              ladder<N, false>(L, I, I, hnx, hny, tnz, nx2, ny2);
               put_level(IC<N>{}, IC<L0>{}, L);
               if constexpr (N < P) {
                 if (N < p) {
                   CArr<T, P1> nQ, nJ, nI;
-                  constexpr T i1 = T(1) / T(N), i2 = T(1) / T(N + 1), i3 = T(1) / T(N + 2);
-                  ladder<N, false>(nQ, Q, Q, vxr[1] * i1, vxi[1] * i1, vz[1] * i1, i1);
-                  ladder<N, true>(nJ, Jj, nQ, vxr[2] * i2, vxi[2] * i2, vz[2] * i2, i2);
-                  ladder<N, true>(nI, I, nJ, vxr[0] * i3, vxi[0] * i3, vz[0] * i3, i3);
+                  Q2X_STEP(nQ, Q, Q, false, 1);
+                  Q2X_STEP(nJ, Jj, nQ, true, 2);
+                  Q2X_STEP(nI, I, nJ, true, 0);
                   Q = nQ;
                   Jj = nJ;
                   I = nI;
@@ -431,7 +452,7 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
       }
     });
   } else if constexpr (KIND == Q2X_SEGMENT) {
-    CArr<T, P1> Q, Pp;
+    CArr<T, P1> Q, Pp;  // q at x2, p from x1 (Lemma 1; Eqs. (50)-(51))
     Q.r[0] = T(1);
     Q.i[0] = T(0);
     Pp.r[0] = T(1);
@@ -446,9 +467,8 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
         } else {
           if constexpr (N >= 1) {
             CArr<T, P1> nQ, nP;
-            constexpr T i1 = T(1) / T(N), i2 = T(1) / T(N + 1);
-            ladder<N, false>(nQ, Q, Q, vxr[1] * i1, vxi[1] * i1, vz[1] * i1, i1);  // q at x2, Eq. (50)
-            ladder<N, true>(nP, Pp, nQ, vxr[0] * i2, vxi[0] * i2, vz[0] * i2, i2);  // p from x1, Eq. (50)
+            Q2X_STEP(nQ, Q, Q, false, 1);
+            Q2X_STEP(nP, Pp, nQ, true, 0);
             Q = nQ;
             Pp = nP;
           }
@@ -457,15 +477,15 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
         }
       }
     });
-  } else {  // Q2X_TET
+  } else {  // Q2X_TET: q at x2, j along x3->x2, b from x4, a from x1 (Eqs. (54)-(55))
     CArr<T, P1> Q, Jj, B, A;
     Q.r[0] = T(1);
     Q.i[0] = T(0);
     Jj.r[0] = T(1);
     Jj.i[0] = T(0);
-    B.r[0] = T(0.5);
+    B.r[0] = T(1);
     B.i[0] = T(0);
-    A.r[0] = T(1) / T(6);
+    A.r[0] = T(1);
     A.i[0] = T(0);
     bool done = false;
     static_for<0, P + 1>([&](auto NN) {
@@ -477,11 +497,10 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
         } else {
           if constexpr (N >= 1) {
             CArr<T, P1> nQ, nJ, nB, nA;
-            constexpr T i1 = T(1) / T(N), i2 = T(1) / T(N + 1), i3 = T(1) / T(N + 2), i4 = T(1) / T(N + 3);
-            ladder<N, false>(nQ, Q, Q, vxr[1] * i1, vxi[1] * i1, vz[1] * i1, i1);   // q at x2
-            ladder<N, true>(nJ, Jj, nQ, vxr[2] * i2, vxi[2] * i2, vz[2] * i2, i2);  // j along x3->x2
-            ladder<N, true>(nB, B, nJ, vxr[3] * i3, vxi[3] * i3, vz[3] * i3, i3);   // b from x4, Eq. (54)
-            ladder<N, true>(nA, A, nB, vxr[0] * i4, vxi[0] * i4, vz[0] * i4, i4);   // a from x1, Eq. (54)
+            Q2X_STEP(nQ, Q, Q, false, 1);
+            Q2X_STEP(nJ, Jj, nQ, true, 2);
+            Q2X_STEP(nB, B, nJ, true, 3);
+            Q2X_STEP(nA, A, nB, true, 0);
             Q = nQ;
             Jj = nJ;
             B = nB;
@@ -493,6 +512,7 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
       }
     });
   }
+#undef Q2X_STEP
 }
 
 }  // namespace q2x

@@ -4,16 +4,18 @@ FLOPs are counted operation by operation as the recursion of Sec. 3.4,
 Eqs. (50)-(56), is evaluated in the m >= 0 form with zero padding pruned
 (entries with m > n are never touched), one FMA = 2 FLOPs:
 
-  ladder step to degree n (one array): 3 multiplies to pre-scale xi, z by
-  1/(n+k); order 0: 1 multiply + 2 doubling adds + 2 FMAs; orders m >= 1:
-  the -xi F^{m-1} + eta F^{m+1} pair costs 10 FLOPs when F^{m+1} exists and
-  6 when it does not, the -z F^m term 4 FLOPs when F^m exists, and the
-  source term (j, i, b, a, p recursions) 4 FLOPs (2 at m = 0).
+  ladder step to degree n (one array): order 0: 1 multiply + 2 FMAs;
+  orders m >= 1: the -xi F^{m-1} + eta F^{m+1} pair costs 10 FLOPs when
+  F^{m+1} exists, 6 when it does not (2 at m = 1, where F^0 is real), the
+  -z F^m term 4 FLOPs when F^m exists, and the source term (j, i, b, a, p
+  recursions) 2 FLOPs (1 at m = 0).
   Per degree:  triangle single = q + j(+q) + i(+j);  segment = q + p(+q);
   tetrahedron = q + j + b + a;  double layer = one D_nu step on i_{n-1}
-  (no pre-scale, no source) plus the q, j, i steps to degree n-1.
-  Weighting: 2 multiplies per staged tilde coefficient; reduction: 2 FP64
-  adds per element-coefficient.  Geometry (~60 FLOPs) is counted once.
+  (no source) plus the q, j, i steps to degree n-1.
+  The recursion runs on G_n = (n+k)! t_n, so it has no per-step constants;
+  the FP64 factor s_e a_e^n/(n+k)! costs 2 multiplies per degree, and the
+  reduction one FP64 FMA per real component of every element-coefficient
+  (4 FLOPs per complex coefficient).  Geometry (~60 FLOPs) is counted once.
 
 Bytes (algorithmic, per launch): inputs read once (per element: k vertex
 indices, density, box id, and k vertices of 24 B counted per element) plus the
@@ -26,20 +28,24 @@ NV = {TRI_SINGLE: 3, TRI_DOUBLE: 3, SEGMENT: 2, TET: 4}
 GEOMETRY_FLOPS = 60
 
 
-def ladder_flops(n: int, add: bool, prescale: bool = True) -> int:
-    f = 3 if prescale else 0
-    # m = 0
-    f += 1
+def ladder_flops(n: int, add: bool, prescale: bool = False) -> int:
+    """FLOPs of one ladder step to degree n of one array (see the module doc)."""
+    f = 1  # order 0: -z F^0
     if n - 1 >= 1:
-        f += 2 + 4
+        f += 4  # 2 xi_r F^1_r + 2 xi_i F^1_i (doubled xi precomputed per element)
     if add:
-        f += 2
+        f += 1
     for m in range(1, n + 1):
-        f += 10 if m + 1 <= n - 1 else 6
+        if m + 1 <= n - 1:
+            f += 10
+        elif m == 1:
+            f += 2
+        else:
+            f += 6
         if m <= n - 1:
             f += 4
         if add:
-            f += 4
+            f += 2
     return f
 
 
@@ -56,7 +62,7 @@ def recursion_flops(kind: int, p: int) -> int:
             f += ladder_flops(n, False) + 3 * ladder_flops(n, True)
     elif kind == TRI_DOUBLE:
         for n in range(1, p + 1):
-            f += ladder_flops(n, False, prescale=False)  # l_n = D_nu i_{n-1}
+            f += ladder_flops(n, False)  # l_n = D_nu i_{n-1}
             if n < p:
                 f += ladder_flops(n, False) + 2 * ladder_flops(n, True)
     else:
@@ -65,9 +71,9 @@ def recursion_flops(kind: int, p: int) -> int:
 
 
 def element_flops(kind: int, p: int) -> int:
-    """Total FLOPs per element: geometry + recursion + weighting + reduction."""
+    """Total FLOPs per element: geometry + recursion + factors + reduction."""
     nct = (p + 1) * (p + 2) // 2
-    return GEOMETRY_FLOPS + recursion_flops(kind, p) + 2 * nct + 2 * nct
+    return GEOMETRY_FLOPS + recursion_flops(kind, p) + 2 * (p + 1) + 4 * nct
 
 
 def launch_flops(kind: int, p: int, n_elems: int) -> int:
