@@ -45,7 +45,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist(const int32_t* __rest
       int32_t k = keys[i];
       if (first_pass) {
         const int32_t kc = clamp_key(k, nb);
-        bad += (kc != k);
+        bad += (k < 0 || k >= nb);
         k = kc;
       }
       atomicAdd(&h[(k >> shift) & (kBins - 1)], 1);

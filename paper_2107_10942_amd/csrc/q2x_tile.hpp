@@ -250,7 +250,9 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
       J = sqrt(ux * ux + uy * uy + uz * uz);
     } else {
       const double vx = xv[2][0] - xv[0][0], vy = xv[2][1] - xv[0][1], vz = xv[2][2] - xv[0][2];
-      const double crx = uy * vz - uz * vy, cry = uz * vx - ux * vz, crz = ux * vy - uy * vx;
+      // products rounded separately (no FMA contraction): a repeated vertex gives J = 0 exactly
+      const double crx = __dmul_rn(uy, vz) - __dmul_rn(uz, vy), cry = __dmul_rn(uz, vx) - __dmul_rn(ux, vz),
+                   crz = __dmul_rn(ux, vy) - __dmul_rn(uy, vx);
       if constexpr (KIND == Q2X_TET) {
         const double wx = xv[3][0] - xv[0][0], wy = xv[3][1] - xv[0][1], wz = xv[3][2] - xv[0][2];
         J = fabs(crx * wx + cry * wy + crz * wz);
