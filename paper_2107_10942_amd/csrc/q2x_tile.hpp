@@ -54,6 +54,16 @@ struct CArr {
   T i[P1];
 };
 
+// Cross product with every product rounded on its own (no FMA contraction),
+// so that u x u is exactly zero and a repeated vertex gives J = 0.
+__device__ __forceinline__ void cross_nofma(double ux, double uy, double uz, double vx, double vy, double vz,
+                                            double& cx, double& cy, double& cz) {
+#pragma clang fp contract(off)
+  cx = uy * vz - uz * vy;
+  cy = uz * vx - ux * vz;
+  cz = ux * vy - uy * vx;
+}
+
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
@@ -250,9 +260,8 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
       J = sqrt(ux * ux + uy * uy + uz * uz);
     } else {
       const double vx = xv[2][0] - xv[0][0], vy = xv[2][1] - xv[0][1], vz = xv[2][2] - xv[0][2];
-      // products rounded separately (no FMA contraction): a repeated vertex gives J = 0 exactly
-      const double crx = __dmul_rn(uy, vz) - __dmul_rn(uz, vy), cry = __dmul_rn(uz, vx) - __dmul_rn(ux, vz),
-                   crz = __dmul_rn(ux, vy) - __dmul_rn(uy, vx);
+      double crx, cry, crz;
+      cross_nofma(ux, uy, uz, vx, vy, vz, crx, cry, crz);
       if constexpr (KIND == Q2X_TET) {
         const double wx = xv[3][0] - xv[0][0], wy = xv[3][1] - xv[0][1], wz = xv[3][2] - xv[0][2];
         J = fabs(crx * wx + cry * wy + crz * wz);
