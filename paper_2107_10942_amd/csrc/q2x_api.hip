@@ -11,10 +11,9 @@
 
 namespace q2x {
 
-hipError_t bucket_elements(const int32_t* elem_box, int64_t n, int64_t nb, int32_t* scratch, int32_t* box_start,
-                           Status* status, hipStream_t s, const int32_t** keys_out, const int32_t** perm_out);
-hipError_t presorted_bounds(const int32_t* elem_box, int64_t n, int64_t nb, int32_t* box_start, Status* status,
-                            hipStream_t s);
+hipError_t bucket_elements(const int32_t* elem_box, int64_t n, int64_t nb, int32_t* scratch, Status* status,
+                           hipStream_t s, const int32_t** keys_out, const int32_t** perm_out);
+hipError_t launch_box_bounds(const int32_t* keys, int64_t n, int64_t nb, int32_t* box_start, hipStream_t s);
 hipError_t clear_status(Status* st, hipStream_t s);
 hipError_t copy_words(int32_t* dst, const int32_t* src, int64_t n, hipStream_t s);
 size_t bucket_scratch_bytes(int64_t n, int64_t nb);
@@ -30,7 +29,7 @@ __global__ __launch_bounds__(256) void q2x_fixup_kernel(FixupArgs f) {
   const int nct_out = tri(f.p + 1);
   const int NCT = tri(f.P + 1);
   for (int64_t b = wave; b < f.n_boxes; b += nwaves) {
-    const int64_t s = f.box_start[b], t = f.box_start[b + 1];
+    const int64_t s = f.n_pos ? f.box_start[b] : 0, t = f.n_pos ? f.box_start[b + 1] : 0;
     double* row = f.coeffs + b * (int64_t)ncoef * 2;
     if (t <= s) {
       if (!f.accumulate)
@@ -159,14 +158,15 @@ q2x_status run(int kind, const double* verts, int64_t n_verts, const int32_t* el
   }
   if (timing) hipEventRecord(ev.a, s);
 
-  if (clear_status(st, s) != hipSuccess) return Q2X_ERR_HIP;
+  // status clear + bucketing (the first sort kernel clears the status block);
+  // the tile kernel writes the box start table
   const int32_t* keys = elem_box;
   const int32_t* perm = nullptr;
   hipError_t err;
-  if (flags & Q2X_PRESORTED) {
-    err = presorted_bounds(elem_box, n_elems, n_boxes, box_start, st, s);
+  if ((flags & Q2X_PRESORTED) || n_elems == 0) {
+    err = clear_status(st, s);
   } else {
-    err = bucket_elements(elem_box, n_elems, n_boxes, sort_scratch, box_start, st, s, &keys, &perm);
+    err = bucket_elements(elem_box, n_elems, n_boxes, sort_scratch, st, s, &keys, &perm);
   }
   if (err != hipSuccess) return Q2X_ERR_HIP;
 
@@ -198,6 +198,7 @@ q2x_status run(int kind, const double* verts, int64_t n_verts, const int32_t* el
     FixupArgs f;
     f.box_start = box_start;
     f.partials = partials;
+    f.n_pos = n_elems;
     f.coeffs = coeffs;
     f.n_boxes = n_boxes;
     f.p = p;
@@ -264,11 +265,14 @@ q2x_status q2x_bucket(const int32_t* elem_box, int64_t n_elems, int64_t n_boxes,
   hipStream_t s = (hipStream_t)stream;
   Status* st = (Status*)workspace;
   int32_t* scratch = (int32_t*)((char*)workspace + align_up(sizeof(Status)));
-  if (clear_status(st, s) != hipSuccess) return Q2X_ERR_HIP;
-  const int32_t* keys = nullptr;
+  const int32_t* keys = elem_box;
   const int32_t* pm = nullptr;
-  if (bucket_elements(elem_box, n_elems, n_boxes, scratch, box_start, st, s, &keys, &pm) != hipSuccess)
+  if (n_elems == 0) {
+    if (clear_status(st, s) != hipSuccess) return Q2X_ERR_HIP;
+  } else if (bucket_elements(elem_box, n_elems, n_boxes, scratch, st, s, &keys, &pm) != hipSuccess) {
     return Q2X_ERR_HIP;
+  }
+  if (launch_box_bounds(keys, n_elems, n_boxes, box_start, s) != hipSuccess) return Q2X_ERR_HIP;
   if (n_elems > 0 && copy_words(perm, pm, n_elems, s) != hipSuccess) return Q2X_ERR_HIP;
   return Q2X_OK;
 }

@@ -34,7 +34,7 @@ struct TileArgs {
   const int32_t* keys;       // box id of each sorted position (elem_box itself when presorted)
   const int32_t* perm;       // sorted position -> element index (nullptr: identity)
   const double* box_center;
-  const int32_t* box_start;  // [n_boxes + 1] start position of each box
+  int32_t* box_start;        // [n_boxes + 1] out: start position of each box
   double* coeffs;            // [n_boxes][(p+1)^2][2]
   double* partials;          // [n_tiles][2][tri(P+1)][2] raw sums of boxes cut by tile edges
   Status* status;
@@ -48,9 +48,10 @@ struct TileArgs {
 
 // Arguments of the fix-up kernel (boxes cut by tile edges, empty boxes).
 struct FixupArgs {
-  const int32_t* box_start;
+  const int32_t* box_start;  // written by the tile kernel (unused when n_pos == 0)
   const double* partials;
   double* coeffs;
+  int64_t n_pos;
   int64_t n_boxes;
   int p;
   int P;                     // bucket order the partials were laid out for

@@ -209,8 +209,8 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
   const int64_t tile = xcd_tile(blockIdx.x, n_tiles);
   const int lane = threadIdx.x;
   const int64_t q0 = tile * kTile;
-  const int64_t pos_end = a.box_start[a.n_boxes];
-  if (q0 >= pos_end) return;  // uniform
+  const int64_t pos_end = a.n_pos;
+  if (q0 >= pos_end) return;  // uniform (never taken with the host's grid)
   const int ne = (int)min<int64_t>(kTile, pos_end - q0);
   const int64_t q = q0 + lane;
   const bool in_range = lane < ne;
@@ -309,6 +309,19 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
   constexpr double inv_depth_fact = (DEPTH == 1) ? 1.0 : (DEPTH == 2) ? 0.5 : 1.0 / 6.0;
   double fpow = ((SHIFT == 1) ? w64 * inv_scl : w64) * inv_depth_fact;
 
+  // ---- box start table: box_start[b] = first position whose key >= b, keys
+  // outside [0, B) counting as -1 / B (the fix-up kernel reads it)
+  const int key_prev = (in_range && q > 0) ? a.keys[q - 1] : INT32_MIN;
+  if (in_range) {
+    const int64_t nb = a.n_boxes;
+    const int64_t kc = key < 0 ? -1 : (key >= nb ? nb : key);
+    const int64_t kp = (q == 0 || key_prev < 0) ? -1 : (key_prev >= nb ? nb : key_prev);
+    if (kp > kc) flag |= Q2X_FLAG_NOT_SORTED;
+    for (int64_t b = kp + 1; b <= kc; ++b) a.box_start[b] = (int32_t)q;
+    if (q == pos_end - 1)
+      for (int64_t b = kc + 1; b <= nb; ++b) a.box_start[b] = (int32_t)pos_end;
+  }
+
   // ---- status (one atomic per wavefront and counter)
   {
     const uint64_t deg_mask = __ballot(degenerate);
@@ -325,7 +338,6 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
   }
 
   // ---- box boundaries inside the tile (uniform bit mask), open tile edges
-  const int key_prev = (in_range && lane > 0) ? a.keys[q - 1] : INT32_MIN;
   const uint64_t bnd = __ballot(in_range && (lane == 0 || key != key_prev));
   bool head_open = false, tail_open = false;
   if (q0 > 0) head_open = (a.keys[q0 - 1] == a.keys[q0]);
