@@ -70,70 +70,49 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t nblk) {
 }
 
 // Turn the raw tilde box sum T_n^m (sum_e s_e t~_{e,n}^m, m >= 0) into the two
-// output coefficients and store (or add) them.
+// output coefficients and store (or add) them.  With i^{-m} = c + i s:
 //   FMM   : F_n^{m}  = (-1)^n i^{-m} conj(T),  F_n^{-m} = (-1)^n i^{-m} T
 //   MOMENT: M_n^{m}  = (-1)^m 4pi i^{m} T,     M_n^{-m} = (-1)^m 4pi i^{m} conj(T)
 // (tilde <-> plain: Sec. 3.4, Eqs. (47),(49); symmetry Eq. (12); weights Eq. (20)).
+// Branch-free in m (lanes of a wavefront hold different orders).
 __device__ __forceinline__ void finalize_store(double* row, int n, int m, double tr, double ti, int norm,
                                                int accumulate) {
-  double a, b;  // value for +m
-  double c, d;  // value for -m
+  const int r = m & 3;
+  const double c = (r == 0) ? 1.0 : ((r == 2) ? -1.0 : 0.0);
+  const double s = (r == 1) ? -1.0 : ((r == 3) ? 1.0 : 0.0);
+  double a, b, cc, d;  // (a, b) for +m, (cc, d) for -m
   if (norm == Q2X_NORM_FMM) {
     const double base = (n & 1) ? -1.0 : 1.0;
-    // i^{-m}: m%4 = 0 -> 1, 1 -> -i, 2 -> -1, 3 -> i
-    const double xr = base * tr, xi = base * ti;  // base * T
-    double pr, pi;                                 // i^{-m} * (base*T)
-    switch (m & 3) {
-      case 0: pr = xr; pi = xi; break;
-      case 1: pr = xi; pi = -xr; break;
-      case 2: pr = -xr; pi = -xi; break;
-      default: pr = -xi; pi = xr; break;
-    }
-    // i^{-m} conj(base*T)
-    double qr, qi;
-    switch (m & 3) {
-      case 0: qr = xr; qi = -xi; break;
-      case 1: qr = -xi; qi = -xr; break;
-      case 2: qr = -xr; qi = xi; break;
-      default: qr = xi; qi = xr; break;
-    }
-    a = qr; b = qi; c = pr; d = pi;
+    const double xr = base * tr, xi = base * ti;
+    a = c * xr + s * xi;   // (c + i s)(xr - i xi)
+    b = s * xr - c * xi;
+    cc = c * xr - s * xi;  // (c + i s)(xr + i xi)
+    d = c * xi + s * xr;
   } else {
     const double base = (m & 1) ? -k4Pi : k4Pi;
     const double xr = base * tr, xi = base * ti;
-    double pr, pi;  // i^{m} * (base*T)
-    switch (m & 3) {
-      case 0: pr = xr; pi = xi; break;
-      case 1: pr = -xi; pi = xr; break;
-      case 2: pr = -xr; pi = -xi; break;
-      default: pr = xi; pi = -xr; break;
-    }
-    double qr, qi;  // i^{m} * conj(base*T)
-    switch (m & 3) {
-      case 0: qr = xr; qi = -xi; break;
-      case 1: qr = xi; qi = xr; break;
-      case 2: qr = -xr; qi = xi; break;
-      default: qr = -xi; qi = -xr; break;
-    }
-    a = pr; b = pi; c = qr; d = qi;
+    a = c * xr + s * xi;   // (c - i s)(xr + i xi)
+    b = c * xi - s * xr;
+    cc = c * xr - s * xi;  // (c - i s)(xr - i xi)
+    d = -c * xi - s * xr;
   }
+  if (m == 0) b = 0.0;  // F_n^0 is real; its imaginary part is round-off
   const int ip = n * n + n + m;
-  if (m == 0) {
-    b = 0.0;  // F_n^0 is real; its imaginary part is round-off
-    if (accumulate) { a += row[2 * ip]; b += row[2 * ip + 1]; }
-    row[2 * ip] = a;
-    row[2 * ip + 1] = b;
-    return;
-  }
   const int im = n * n + n - m;
   if (accumulate) {
-    a += row[2 * ip]; b += row[2 * ip + 1];
-    c += row[2 * im]; d += row[2 * im + 1];
+    a += row[2 * ip];
+    b += row[2 * ip + 1];
   }
   row[2 * ip] = a;
   row[2 * ip + 1] = b;
-  row[2 * im] = c;
-  row[2 * im + 1] = d;
+  if (m != 0) {
+    if (accumulate) {
+      cc += row[2 * im];
+      d += row[2 * im + 1];
+    }
+    row[2 * im] = cc;
+    row[2 * im + 1] = d;
+  }
 }
 
 // Degree and order of the g-th tilde coefficient (g = tri(n) + m).

@@ -10,14 +10,15 @@
 // distance from c, so nothing underflows whatever the element's size and
 // position (degree n of the result scales as a_e^n); the FP64 path runs on
 // x - c unscaled.
-// Every degree's outputs go to an LDS stage, and the FP64 factor
-// s_e a_e^n / (n+k)! (s_e = sigma_e J_e / 4pi) to a small table beside it.  When a
-// group of degrees ("chunk", <= CMAX coefficients) is complete the wavefront
-// transposes through LDS -- lane = coefficient -- and walks the 64 elements in
-// order, one box segment at a time, summing factor * value in FP64.  Boxes
-// wholly inside the tile are finalised and stored directly; a box cut by a
-// tile edge leaves a raw partial sum for the fix-up kernel.  The order of every
-// sum is fixed by the element order, so results are bitwise reproducible.
+// Every degree's outputs go to an LDS stage (real and imaginary parts in
+// separate rows), and the FP64 factor s_e a_e^n / (n+k)!
+// (s_e = sigma_e J_e / 4pi) to a small table beside it.  When a group of
+// degrees ("chunk", <= CMAX coefficients) is complete the wavefront transposes
+// through LDS -- lane = coefficient -- and walks the 64 elements in order, one
+// box segment at a time, summing factor * value in FP64.  Boxes wholly inside
+// the tile are finalised and stored directly; a box cut by a tile edge leaves
+// a raw partial sum for the fix-up kernel.  The order of every sum is fixed by
+// the element order, so results are bitwise reproducible.
 #pragma once
 
 #include "q2x_internal.hpp"
@@ -36,17 +37,6 @@ __device__ __forceinline__ void static_for(F&& f) {
     static_for<B + 1, E>(f);
   }
 }
-
-template <typename T>
-struct Cx2;
-template <>
-struct Cx2<float> {
-  using type = float2;
-};
-template <>
-struct Cx2<double> {
-  using type = double2;
-};
 
 template <typename T, int P1>
 struct CArr {
@@ -71,50 +61,49 @@ __device__ __forceinline__ double fmaT(double a, double b, double c) { return __
 // form), producing degree N (orders 0..N) from degree N-1 (orders 0..N-1):
 //   out^0 = 2 Re(eta F^1) - z F^0 + add^0
 //   out^m = -xi F^{m-1} + eta F^{m+1} - z F^m + add^m,   m >= 1,
-// with xi = (Y_x + i Y_y)/2, eta = conj(xi), z = Y_z and F^k = 0 for k > N-1.
-// The recursions of Eqs. (50)-(55) divide this by (n+k) at the k-th nesting
-// level; the kernel carries G_n = (n+k)! F_n instead, for which the division
-// disappears (G_n = D G_{n-1} + G^{(k-1)}_n, every start value 1), and folds
-// 1/(n+k)! into the FP64 per-degree factor.  (sxr2, sxi2) = 2 (sxr, sxi).
+// with xi = (Y_x + i Y_y)/2 = xr + i xi, eta = conj(xi), z = Y_z and F^k = 0
+// for k > N-1.  The recursions of Eqs. (50)-(55) divide this by (n+k) at the
+// k-th nesting level; the kernel carries G_n = (n+k)! F_n instead, for which
+// the division disappears (G_n = D G_{n-1} + G^{(k-1)}_n, every start value 1),
+// and folds 1/(n+k)! into the FP64 per-degree factor.  Every real output is a
+// chain of FMAs (5 for an interior order with a source term).
+// (xr2, xi2) = 2 (xr, xi).
 template <int N, bool ADD, typename T, int P1>
-__device__ __forceinline__ void ladder(CArr<T, P1>& out, const CArr<T, P1>& F, const CArr<T, P1>& add, T sxr,
-                                       T sxi, T sz, T sxr2, T sxi2) {
+__device__ __forceinline__ void ladder(CArr<T, P1>& out, const CArr<T, P1>& F, const CArr<T, P1>& add, T xr, T xi,
+                                       T z, T xr2, T xi2) {
   static_assert(N >= 1 && N < P1, "degree out of range");
   {
-    T v = -sz * F.r[0];
+    T v = ADD ? fmaT(-z, F.r[0], add.r[0]) : -z * F.r[0];
     if constexpr (N - 1 >= 1) {
-      v = fmaT(sxr2, F.r[1], v);
-      v = fmaT(sxi2, F.i[1], v);
+      v = fmaT(xr2, F.r[1], v);
+      v = fmaT(xi2, F.i[1], v);
     }
-    if constexpr (ADD) v = v + add.r[0];
     out.r[0] = v;
     out.i[0] = T(0);
   }
   static_for<1, N + 1>([&](auto MM) {
     constexpr int m = decltype(MM)::value;
     const T amr = F.r[m - 1];
-    const T ami = (m - 1 == 0) ? T(0) : F.i[m - 1];
-    T re, im;
+    // -xi F^{m-1}:  re -= xr Ar - xi Ai ;  im -= xr Ai + xi Ar
+    T re = ADD ? fmaT(-xr, amr, add.r[m]) : -xr * amr;
+    T im = ADD ? fmaT(-xi, amr, add.i[m]) : -xi * amr;
+    if constexpr (m - 1 > 0) {
+      const T ami = F.i[m - 1];
+      re = fmaT(xi, ami, re);
+      im = fmaT(-xr, ami, im);
+    }
+    // eta F^{m+1}:  re += xr Br + xi Bi ;  im += xr Bi - xi Br
     if constexpr (m + 1 <= N - 1) {
       const T apr = F.r[m + 1], api = F.i[m + 1];
-      re = sxr * (apr - amr);
-      re = fmaT(sxi, ami + api, re);
-      im = sxr * (api - ami);
-      im = fmaT(-sxi, amr + apr, im);
-    } else if constexpr (m - 1 == 0) {
-      re = -sxr * amr;
-      im = -sxi * amr;
-    } else {
-      re = fmaT(-sxr, amr, sxi * ami);
-      im = fmaT(-sxr, ami, -sxi * amr);
+      re = fmaT(xr, apr, re);
+      re = fmaT(xi, api, re);
+      im = fmaT(xr, api, im);
+      im = fmaT(-xi, apr, im);
     }
+    // -z F^m
     if constexpr (m <= N - 1) {
-      re = fmaT(-sz, F.r[m], re);
-      im = fmaT(-sz, F.i[m], im);
-    }
-    if constexpr (ADD) {
-      re = re + add.r[m];
-      im = im + add.i[m];
+      re = fmaT(-z, F.r[m], re);
+      im = fmaT(-z, F.i[m], im);
     }
     out.r[m] = re;
     out.i[m] = im;
@@ -147,34 +136,32 @@ struct ChunkPlan {
   }
 };
 
-// nv: vertices; shift: degree n of the output scales as a^(n - shift);
-// depth: the output at degree n is G / (n + depth)!  (double layer: the
-// degree-n output is D_nu applied to G_i at degree n-1, i.e. divided by (n+1)!).
+// The recursion chain of each element kind (Sec. 3.4): array k of the chain is
+// laddered about vertex vert(k) and fed by array k-1; the output is the last
+// array (for the double layer: D_nu of the last array one degree lower).
+//   nv: vertices; shift: degree n of the output scales as a^(n - shift);
+//   depth: the output at degree n is G / (n + depth)!.
 template <int KIND>
 struct KindInfo;
 template <>
-struct KindInfo<Q2X_TRI_SINGLE> {
-  static constexpr int nv = 3;
-  static constexpr int shift = 0;
-  static constexpr int depth = 2;
+struct KindInfo<Q2X_TRI_SINGLE> {  // q at x2, j along x3->x2, i from x1 (Eqs. (50)-(53))
+  static constexpr int nv = 3, shift = 0, depth = 2, nch = 3;
+  static constexpr int vert(int k) { return k == 0 ? 1 : (k == 1 ? 2 : 0); }
 };
 template <>
-struct KindInfo<Q2X_TRI_DOUBLE> {
-  static constexpr int nv = 3;
-  static constexpr int shift = 1;
-  static constexpr int depth = 1;
+struct KindInfo<Q2X_TRI_DOUBLE> {  // the same chain; output Eq. (56)
+  static constexpr int nv = 3, shift = 1, depth = 1, nch = 3;
+  static constexpr int vert(int k) { return k == 0 ? 1 : (k == 1 ? 2 : 0); }
 };
 template <>
-struct KindInfo<Q2X_SEGMENT> {
-  static constexpr int nv = 2;
-  static constexpr int shift = 0;
-  static constexpr int depth = 1;
+struct KindInfo<Q2X_SEGMENT> {  // q at x2, p from x1 (Eqs. (50)-(51))
+  static constexpr int nv = 2, shift = 0, depth = 1, nch = 2;
+  static constexpr int vert(int k) { return k == 0 ? 1 : 0; }
 };
 template <>
-struct KindInfo<Q2X_TET> {
-  static constexpr int nv = 4;
-  static constexpr int shift = 0;
-  static constexpr int depth = 3;
+struct KindInfo<Q2X_TET> {  // q at x2, j along x3->x2, b from x4, a from x1 (Eqs. (54)-(55))
+  static constexpr int nv = 4, shift = 0, depth = 3, nch = 4;
+  static constexpr int vert(int k) { return k == 0 ? 1 : (k == 1 ? 2 : (k == 2 ? 3 : 0)); }
 };
 
 template <typename T>
@@ -192,10 +179,12 @@ struct PrecInfo<double> {
 
 template <int P, int KIND, typename T>
 __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_tiles) {
-  using C2 = typename Cx2<T>::type;
+  using KI = KindInfo<KIND>;
   constexpr int P1 = P + 1;
-  constexpr int NV = KindInfo<KIND>::nv;
-  constexpr int SHIFT = KindInfo<KIND>::shift;
+  constexpr int NV = KI::nv;
+  constexpr int NCH = KI::nch;
+  constexpr int SHIFT = KI::shift;
+  constexpr int DEPTH = KI::depth;
   constexpr int CMAX = (PrecInfo<T>::cmax > P + 1) ? PrecInfo<T>::cmax : P + 1;
   constexpr int SSTR = kTile + 1;  // padded row stride (elements) of the stage and factor tables
   constexpr int NCT = tri(P + 1);
@@ -203,7 +192,8 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
   using Plan = ChunkPlan<P, CMAX>;
   constexpr int DMAX = Plan::max_degrees();
 
-  __shared__ C2 stage[CMAX * SSTR];
+  // stage: real part of chunk coefficient c in row 2c, imaginary part in row 2c+1
+  __shared__ T stage[2 * CMAX * SSTR];
   __shared__ double fac[DMAX * SSTR];
 
   const int64_t tile = xcd_tile(blockIdx.x, n_tiles);
@@ -305,7 +295,6 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
     vxi2[k] = (T)(X[k][1] * inv_scl);
   }
   // running FP64 factor s_e a_e^(n - SHIFT) / (n + DEPTH)! of the degree being produced
-  constexpr int DEPTH = KindInfo<KIND>::depth;
   constexpr double inv_depth_fact = (DEPTH == 1) ? 1.0 : (DEPTH == 2) ? 0.5 : 1.0 / 6.0;
   double fpow = ((SHIFT == 1) ? w64 * inv_scl : w64) * inv_depth_fact;
 
@@ -358,7 +347,7 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
     int n = 0, m = 0;
     tri_nm(CB + (act ? c : 0), n, m);
     const bool wr = act && n <= p;
-    const C2* srow = stage + (act ? c : 0) * SSTR;
+    const T* srow = stage + 2 * (act ? c : 0) * SSTR;
     const double* frow = fac + (n - L0) * SSTR;
     int sa = 0;
     while (sa < ne) {  // uniform: one box segment [sa, sb) per iteration
@@ -367,10 +356,9 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
       double accr = 0.0, acci = 0.0;
 #pragma unroll 4
       for (int el = sa; el < sb; ++el) {
-        const C2 v = srow[el];
         const double f = frow[el];
-        accr = __builtin_fma((double)v.x, f, accr);
-        acci = __builtin_fma((double)v.y, f, acci);
+        accr = __builtin_fma((double)srow[el], f, accr);
+        acci = __builtin_fma((double)srow[SSTR + el], f, acci);
       }
       const int box = __builtin_amdgcn_readlane(key, sa);
       if (box >= 0 && box < a.n_boxes && wr) {
@@ -389,24 +377,20 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
     __syncthreads();
   };
 
-  // stage degree N's outputs (unweighted) and its FP64 factor
-  auto put_level = [&](auto NNc, auto L0c, const CArr<T, P1>& V) {
+  // stage degree N's outputs and its FP64 factor; reduce at chunk ends (and at
+  // the requested order when it falls inside a chunk)
+  auto put_level = [&](auto NNc, const CArr<T, P1>& V) {
     constexpr int N = decltype(NNc)::value;
-    constexpr int L0 = decltype(L0c)::value;
+    constexpr int L0 = Plan::first_level(N);
     static_for<0, N + 1>([&](auto MM) {
       constexpr int m = decltype(MM)::value;
-      C2 v;
-      v.x = V.r[m];
-      v.y = V.i[m];
-      stage[(tri(N) - tri(L0) + m) * SSTR + lane] = v;
+      constexpr int row = 2 * (tri(N) - tri(L0) + m);
+      stage[row * SSTR + lane] = V.r[m];
+      stage[(row + 1) * SSTR + lane] = V.i[m];
     });
     fac[(N - L0) * SSTR + lane] = fpow;
     constexpr double inv_next = 1.0 / (double)(N + 1 + DEPTH);
     fpow = fpow * scl * inv_next;
-  };
-  auto end_level = [&](auto NNc) {
-    constexpr int N = decltype(NNc)::value;
-    constexpr int L0 = Plan::first_level(N);
     if constexpr (Plan::is_end(N)) {
       reduce_chunk(IC<L0>{}, IC<N>{});
     } else if (N == p) {
@@ -414,128 +398,68 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
     }
   };
 
-  // ---- recursion over degrees (Sec. 3.4), on G_n = (n+k)! F_n (see ladder())
-  // ladder step of array `dst` about vertex v (0-based), adding `src` when given
-#define Q2X_STEP(dst, prev, src, ADDF, v) \
-  ladder<N, ADDF>(dst, prev, src, vxr[v], vxi[v], vz[v], vxr2[v], vxi2[v])
-  if constexpr (KIND == Q2X_TRI_SINGLE || KIND == Q2X_TRI_DOUBLE) {
-    CArr<T, P1> Q, Jj, I;  // q at x2 (Eqs. (40)-(41)), j along x3->x2, i from x1 (Eqs. (50)-(53))
-    Q.r[0] = T(1);
-    Q.i[0] = T(0);
-    Jj.r[0] = T(1);
-    Jj.i[0] = T(0);
-    I.r[0] = T(1);
-    I.i[0] = T(0);
-    const T hnx = (T)(0.5 * nx), hny = (T)(0.5 * ny), tnz = (T)nz, nx2 = (T)nx, ny2 = (T)ny;
-    bool done = false;
-    static_for<0, P + 1>([&](auto NN) {
-      constexpr int N = decltype(NN)::value;
-      constexpr int L0 = Plan::first_level(N);
-      if (!done) {
-        if (N > p) {
-          done = true;
-        } else {
-          if constexpr (KIND == Q2X_TRI_SINGLE) {
-            if constexpr (N >= 1) {
-              CArr<T, P1> nQ, nJ, nI;
-              Q2X_STEP(nQ, Q, Q, false, 1);
-              Q2X_STEP(nJ, Jj, nQ, true, 2);
-              Q2X_STEP(nI, I, nJ, true, 0);
-              Q = nQ;
-              Jj = nJ;
-              I = nI;
-            }
-            put_level(IC<N>{}, IC<L0>{}, I);
-          } else {
-            // double layer: l~_N = D_nu i~_{N-1}, nu = (n_x + i n_y)/2 (Sec. 3.4, Eq. (56))
-            if constexpr (N == 0) {
-              CArr<T, P1> Z;
-              Z.r[0] = T(0);
-              Z.i[0] = T(0);
-              put_level(IC<0>{}, IC<L0>{}, Z);
-            } else {
-              CArr<T, P1> L;
-              ladder<N, false>(L, I, I, hnx, hny, tnz, nx2, ny2);
-              put_level(IC<N>{}, IC<L0>{}, L);
-              if constexpr (N < P) {
-                if (N < p) {
-                  CArr<T, P1> nQ, nJ, nI;
-                  Q2X_STEP(nQ, Q, Q, false, 1);
-                  Q2X_STEP(nJ, Jj, nQ, true, 2);
-                  Q2X_STEP(nI, I, nJ, true, 0);
-                  Q = nQ;
-                  Jj = nJ;
-                  I = nI;
-                }
-              }
-            }
-          }
-          end_level(IC<N>{});
-        }
-      }
+  // one degree of every array of the chain: nS (degree N) from S (degree N-1)
+  auto advance = [&](auto NNc, CArr<T, P1>(&nS)[NCH], const CArr<T, P1>(&S)[NCH]) {
+    constexpr int N = decltype(NNc)::value;
+    static_for<0, NCH>([&](auto KK) {
+      constexpr int k = decltype(KK)::value;
+      constexpr int v = KI::vert(k);
+      if constexpr (k == 0)
+        ladder<N, false>(nS[0], S[0], S[0], vxr[v], vxi[v], vz[v], vxr2[v], vxi2[v]);
+      else
+        ladder<N, true>(nS[k], S[k], nS[k - 1], vxr[v], vxi[v], vz[v], vxr2[v], vxi2[v]);
     });
-  } else if constexpr (KIND == Q2X_SEGMENT) {
-    CArr<T, P1> Q, Pp;  // q at x2, p from x1 (Lemma 1; Eqs. (50)-(51))
-    Q.r[0] = T(1);
-    Q.i[0] = T(0);
-    Pp.r[0] = T(1);
-    Pp.i[0] = T(0);
-    bool done = false;
-    static_for<0, P + 1>([&](auto NN) {
-      constexpr int N = decltype(NN)::value;
-      constexpr int L0 = Plan::first_level(N);
-      if (!done) {
-        if (N > p) {
-          done = true;
-        } else {
-          if constexpr (N >= 1) {
-            CArr<T, P1> nQ, nP;
-            Q2X_STEP(nQ, Q, Q, false, 1);
-            Q2X_STEP(nP, Pp, nQ, true, 0);
-            Q = nQ;
-            Pp = nP;
-          }
-          put_level(IC<N>{}, IC<L0>{}, Pp);
-          end_level(IC<N>{});
-        }
-      }
-    });
-  } else {  // Q2X_TET: q at x2, j along x3->x2, b from x4, a from x1 (Eqs. (54)-(55))
-    CArr<T, P1> Q, Jj, B, A;
-    Q.r[0] = T(1);
-    Q.i[0] = T(0);
-    Jj.r[0] = T(1);
-    Jj.i[0] = T(0);
-    B.r[0] = T(1);
-    B.i[0] = T(0);
-    A.r[0] = T(1);
-    A.i[0] = T(0);
-    bool done = false;
-    static_for<0, P + 1>([&](auto NN) {
-      constexpr int N = decltype(NN)::value;
-      constexpr int L0 = Plan::first_level(N);
-      if (!done) {
-        if (N > p) {
-          done = true;
-        } else {
-          if constexpr (N >= 1) {
-            CArr<T, P1> nQ, nJ, nB, nA;
-            Q2X_STEP(nQ, Q, Q, false, 1);
-            Q2X_STEP(nJ, Jj, nQ, true, 2);
-            Q2X_STEP(nB, B, nJ, true, 3);
-            Q2X_STEP(nA, A, nB, true, 0);
-            Q = nQ;
-            Jj = nJ;
-            B = nB;
-            A = nA;
-          }
-          put_level(IC<N>{}, IC<L0>{}, A);
-          end_level(IC<N>{});
-        }
-      }
-    });
+  };
+
+  // ---- recursion over degrees (Sec. 3.4).  Nested rather than sequential, so
+  // that skipping the degrees above p merges no register state.
+  CArr<T, P1> S0[NCH];
+#pragma unroll
+  for (int k = 0; k < NCH; ++k) {
+    S0[k].r[0] = T(1);
+    S0[k].i[0] = T(0);
   }
-#undef Q2X_STEP
+  if constexpr (KIND != Q2X_TRI_DOUBLE) {
+    // S holds degree N; stage the chain's last array
+    auto rec = [&](auto self, auto NNc, const CArr<T, P1>(&S)[NCH]) -> void {
+      constexpr int N = decltype(NNc)::value;
+      put_level(IC<N>{}, S[NCH - 1]);
+      if constexpr (N < P) {
+        if (N < p) {
+          CArr<T, P1> nS[NCH];
+          advance(IC<N + 1>{}, nS, S);
+          self(self, IC<N + 1>{}, nS);
+        }
+      }
+    };
+    rec(rec, IC<0>{}, S0);
+  } else {
+    // double layer: l~_N = D_nu i~_{N-1}, nu = (n_x + i n_y)/2 (Sec. 3.4, Eq. (56));
+    // S holds degree max(N-1, 0)
+    const T hnx = (T)(0.5 * nx), hny = (T)(0.5 * ny), tnz = (T)nz, nx2 = (T)nx, ny2 = (T)ny;
+    auto rec = [&](auto self, auto NNc, const CArr<T, P1>(&S)[NCH]) -> void {
+      constexpr int N = decltype(NNc)::value;
+      if constexpr (N == 0) {
+        CArr<T, P1> Z;
+        Z.r[0] = T(0);
+        Z.i[0] = T(0);
+        put_level(IC<0>{}, Z);
+        if (0 < p) self(self, IC<1>{}, S);
+      } else {
+        CArr<T, P1> L;
+        ladder<N, false>(L, S[NCH - 1], S[NCH - 1], hnx, hny, tnz, nx2, ny2);
+        put_level(IC<N>{}, L);
+        if constexpr (N < P) {
+          if (N < p) {
+            CArr<T, P1> nS[NCH];
+            advance(IC<N>{}, nS, S);
+            self(self, IC<N + 1>{}, nS);
+          }
+        }
+      }
+    };
+    rec(rec, IC<0>{}, S0);
+  }
 }
 
 }  // namespace q2x
