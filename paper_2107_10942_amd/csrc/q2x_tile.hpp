@@ -169,7 +169,9 @@ struct PrecInfo;
 template <>
 struct PrecInfo<float> {
   static constexpr bool scaled = true;  // FP32 recursion on (y - c)/a_e
-  static constexpr int cmax = 64;
+  // 31 coefficients per chunk keep the stage + factor table within 20 KB, so
+  // two wavefronts fit per SIMD (160 KB LDS per CU)
+  static constexpr int cmax = 31;
 };
 template <>
 struct PrecInfo<double> {
@@ -192,9 +194,10 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
   using Plan = ChunkPlan<P, CMAX>;
   constexpr int DMAX = Plan::max_degrees();
 
-  // stage: real part of chunk coefficient c in row 2c, imaginary part in row 2c+1
+  // stage: real part of chunk coefficient c in row c, imaginary part in row CMAX + c
   __shared__ T stage[2 * CMAX * SSTR];
   __shared__ double fac[DMAX * SSTR];
+  __shared__ int tkey[kTile];  // box id of every element of the tile
 
   const int64_t tile = xcd_tile(blockIdx.x, n_tiles);
   const int lane = threadIdx.x;
@@ -328,51 +331,96 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
 
   // ---- box boundaries inside the tile (uniform bit mask), open tile edges
   const uint64_t bnd = __ballot(in_range && (lane == 0 || key != key_prev));
+  tkey[lane] = key;  // read after the barrier that opens every chunk reduction
   bool head_open = false, tail_open = false;
   if (q0 > 0) head_open = (a.keys[q0 - 1] == a.keys[q0]);
   if (ne == kTile && q0 + kTile < pos_end) tail_open = (a.keys[q0 + kTile] == a.keys[q0 + kTile - 1]);
   const int p = a.p;
   const int ncoef_out = (p + 1) * (p + 1);
 
-  // ---- reduction of one chunk of degrees [L0, L1] (lane = coefficient)
+  // ---- reduction of one chunk of degrees [L0, L1]
+  // lane = (group g, coefficient c): with CMAX <= 32 the two half-waves walk
+  // elements [0,32) and [32,64) of the same coefficient (G = 2), otherwise one
+  // lane walks all 64 (G = 1).  Within a group every box segment is summed in
+  // element order and flushed where it ends; the one segment that may straddle
+  // the halves is summed by both and joined (tail of half 0 + head of half 1).
+  auto flush = [&](int sa, int sb, double accr, double acci, bool wr, int n, int m, int g_coef) {
+    const int box = tkey[sa];  // (an LDS table: flushes run in lane-divergent code)
+    if (!(wr && box >= 0 && box < a.n_boxes)) return;
+    const bool open = (sa == 0 && head_open) || (sb == kTile && tail_open);
+    if (open) {
+      const int slot = (sa == 0) ? 0 : 1;
+      double* pp = a.partials + ((tile * 2 + slot) * (int64_t)NCT + g_coef) * 2;
+      pp[0] = accr;
+      pp[1] = acci;
+    } else {
+      finalize_store(a.coeffs + (int64_t)box * ncoef_out * 2, n, m, accr, acci, a.norm, a.accumulate);
+    }
+  };
   auto reduce_chunk = [&](auto L0c, auto L1c) {
     constexpr int L0 = decltype(L0c)::value;
     constexpr int L1 = decltype(L1c)::value;
     constexpr int CB = tri(L0);
     constexpr int C = tri(L1 + 1) - tri(L0);
     static_assert(C <= CMAX && L1 - L0 + 1 <= DMAX, "chunk too large");
+    constexpr int G = (CMAX <= 32) ? 2 : 1;
+    constexpr int E = kTile / G;
     __syncthreads();
-    const int c = lane;
+    const int g = (G == 2) ? (lane >> 5) : 0;
+    const int c = (G == 2) ? (lane & 31) : lane;
     const bool act = c < C;
+    const int cc = act ? c : 0;
     int n = 0, m = 0;
-    tri_nm(CB + (act ? c : 0), n, m);
+    tri_nm(CB + cc, n, m);
     const bool wr = act && n <= p;
-    const T* srow = stage + 2 * (act ? c : 0) * SSTR;
+    const T* rre = stage + cc * SSTR;
+    const T* rim = stage + (CMAX + cc) * SSTR;
     const double* frow = fac + (n - L0) * SSTR;
-    int sa = 0;
-    while (sa < ne) {  // uniform: one box segment [sa, sb) per iteration
-      const uint64_t later = (sa + 1 < 64) ? (bnd >> (sa + 1)) : 0ull;
-      const int sb = later ? sa + 1 + __builtin_ctzll(later) : ne;
-      double accr = 0.0, acci = 0.0;
+    const int gs = g * E;
+    const int ge = min(gs + E, ne);
+    const bool cont_in = (g > 0) && (gs < ne) && !((bnd >> gs) & 1ull);
+    double accr = 0.0, acci = 0.0, hr = 0.0, hi = 0.0;
+    int seg = gs, head_end = ge;
+    bool in_head = cont_in;
 #pragma unroll 4
-      for (int el = sa; el < sb; ++el) {
-        const double f = frow[el];
-        accr = __builtin_fma((double)srow[el], f, accr);
-        acci = __builtin_fma((double)srow[SSTR + el], f, acci);
-      }
-      const int box = __builtin_amdgcn_readlane(key, sa);
-      if (box >= 0 && box < a.n_boxes && wr) {
-        const bool open = (sa == 0 && head_open) || (sb == kTile && tail_open);
-        if (open) {
-          const int slot = (sa == 0) ? 0 : 1;
-          double* pp = a.partials + ((tile * 2 + slot) * (int64_t)NCT + CB + c) * 2;
-          pp[0] = accr;
-          pp[1] = acci;
-        } else {
-          finalize_store(a.coeffs + (int64_t)box * ncoef_out * 2, n, m, accr, acci, a.norm, a.accumulate);
+    for (int i = 0; i < E; ++i) {
+      const int el = gs + i;
+      if (el < ge) {
+        if (i > 0 && ((bnd >> el) & 1ull)) {
+          if (in_head) {  // the continued segment ends inside this half: keep it for the join
+            hr = accr;
+            hi = acci;
+            head_end = el;
+            in_head = false;
+          } else {
+            flush(seg, el, accr, acci, wr, n, m, CB + c);
+          }
+          accr = 0.0;
+          acci = 0.0;
+          seg = el;
         }
+        const double f = frow[el];
+        accr = __builtin_fma((double)rre[el], f, accr);
+        acci = __builtin_fma((double)rim[el], f, acci);
       }
-      sa = sb;
+    }
+    // last segment of the half: flushed here unless it is joined with the other half
+    const bool cont_out = (G == 2) && (g == 0) && (ge == E) && (E < ne) && !((bnd >> E) & 1ull);
+    if (gs < ne) {
+      if (in_head) {  // continued segment covers the rest of half 1
+        hr = accr;
+        hi = acci;
+        head_end = ge;
+      } else if (!cont_out) {
+        flush(seg, ge, accr, acci, wr, n, m, CB + c);
+      }
+    }
+    if constexpr (G == 2) {
+      // join: half 0's open tail + half 1's head (lane c+32 -> lane c)
+      const double jr = __shfl(hr, lane + 32);
+      const double ji = __shfl(hi, lane + 32);
+      const int jend = __shfl(head_end, lane + 32);
+      if (cont_out) flush(seg, jend, accr + jr, acci + ji, wr, n, m, CB + c);
     }
     __syncthreads();
   };
@@ -384,9 +432,9 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
     constexpr int L0 = Plan::first_level(N);
     static_for<0, N + 1>([&](auto MM) {
       constexpr int m = decltype(MM)::value;
-      constexpr int row = 2 * (tri(N) - tri(L0) + m);
+      constexpr int row = tri(N) - tri(L0) + m;
       stage[row * SSTR + lane] = V.r[m];
-      stage[(row + 1) * SSTR + lane] = V.i[m];
+      stage[(CMAX + row) * SSTR + lane] = V.i[m];
     });
     fac[(N - L0) * SSTR + lane] = fpow;
     constexpr double inv_next = 1.0 / (double)(N + 1 + DEPTH);
