@@ -382,27 +382,40 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
     double accr = 0.0, acci = 0.0, hr = 0.0, hi = 0.0;
     int seg = gs, head_end = ge;
     bool in_head = cont_in;
+    // Walk i = 0..E-1 (element gs + i) in pieces cut at every boundary of
+    // either half, so that each piece is a tight loop with uniform control;
+    // at a cut only the half whose box changes there closes its segment.
+    // Elements past ne carry weight 0 and add exact zeros.
+    const uint64_t mybits = (G == 2) ? (bnd >> gs) : bnd;  // this half's boundaries at i
+    const uint64_t cuts = ((G == 2) ? ((bnd | (bnd >> 32)) & 0xffffffffull) : bnd) & ~1ull;
+    const T* pre = rre + gs;
+    const T* pim = rim + gs;
+    const double* pf = frow + gs;
+    int i0 = 0;
+    while (i0 < E) {  // uniform
+      const uint64_t nxt = (i0 + 1 < 64) ? (cuts >> (i0 + 1)) : 0ull;
+      const int i1 = nxt ? i0 + 1 + __builtin_ctzll(nxt) : E;
 #pragma unroll 4
-    for (int i = 0; i < E; ++i) {
-      const int el = gs + i;
-      if (el < ge) {
-        if (i > 0 && ((bnd >> el) & 1ull)) {
-          if (in_head) {  // the continued segment ends inside this half: keep it for the join
-            hr = accr;
-            hi = acci;
-            head_end = el;
-            in_head = false;
-          } else {
-            flush(seg, el, accr, acci, wr, n, m, CB + c);
-          }
-          accr = 0.0;
-          acci = 0.0;
-          seg = el;
-        }
-        const double f = frow[el];
-        accr = __builtin_fma((double)rre[el], f, accr);
-        acci = __builtin_fma((double)rim[el], f, acci);
+      for (int i = i0; i < i1; ++i) {
+        const double f = pf[i];
+        accr = __builtin_fma((double)pre[i], f, accr);
+        acci = __builtin_fma((double)pim[i], f, acci);
       }
+      if (i1 < E && ((mybits >> i1) & 1ull)) {  // this half's segment ends at gs + i1
+        const int el = gs + i1;
+        if (in_head) {  // the continued segment ends inside this half: keep it for the join
+          hr = accr;
+          hi = acci;
+          head_end = el;
+          in_head = false;
+        } else {
+          flush(seg, el, accr, acci, wr, n, m, CB + c);
+        }
+        accr = 0.0;
+        acci = 0.0;
+        seg = el;
+      }
+      i0 = i1;
     }
     // last segment of the half: flushed here unless it is joined with the other half
     const bool cont_out = (G == 2) && (g == 0) && (ge == E) && (E < ne) && !((bnd >> E) & 1ull);
