@@ -2,9 +2,11 @@
 """Q2X benchmark: coefficients/s at p = 16 on the 81,920-triangle perturbed
 sphere (single + double layer, octree level 5), FP32-mixed vs plain FP64.
 
-One step = q2x_tri_single + q2x_tri_double over the whole mesh (bucketing,
-recursion + box reduction, fix-up), inputs resident in HBM.  Prints ONE JSON
-line.  Only N = 1 GPU is supported.
+One step = q2x_tri_both over the whole mesh: one bucketing, one recursion
+producing the single- and double-layer coefficients of every box, one fix-up;
+inputs resident in HBM.  The same work as two separate calls
+(q2x_tri_single + q2x_tri_double) is timed beside it.  Prints ONE JSON line.
+Only N = 1 GPU is supported.
 """
 from __future__ import annotations
 
@@ -60,18 +62,24 @@ def main():
     dens2 = torch.as_tensor(double.density, dtype=torch.float64, device=dev)
     outs = {k: torch.empty((B, (p + 1) ** 2, 2), dtype=torch.float64, device=dev) for k in (0, 1)}
 
-    def make_step(prec):
-        ws = {k: q2x.alloc_workspace(k, N, B, p, prec, device=dev) for k in (0, 1)}
+    def make_step(prec, fused):
         v, e, d, eb, bc, br = ts
+        if fused:
+            ws = {q2x.TRI_BOTH: q2x.alloc_workspace(q2x.TRI_BOTH, N, B, p, prec, device=dev)}
 
-        def step():
-            q2x.run(q2x.TRI_SINGLE, v, e, d, eb, bc, br, p, precision=prec, out=outs[0], workspace=ws[0])
-            q2x.run(q2x.TRI_DOUBLE, v, e, dens2, eb, bc, br, p, precision=prec, out=outs[1], workspace=ws[1])
+            def step():
+                q2x.tri_both(v, e, d, dens2, eb, bc, br, p, precision=prec, out_single=outs[0],
+                             out_double=outs[1], workspace=ws[q2x.TRI_BOTH])
+        else:
+            ws = {k: q2x.alloc_workspace(k, N, B, p, prec, device=dev) for k in (0, 1)}
+
+            def step():
+                q2x.run(q2x.TRI_SINGLE, v, e, d, eb, bc, br, p, precision=prec, out=outs[0], workspace=ws[0])
+                q2x.run(q2x.TRI_DOUBLE, v, e, dens2, eb, bc, br, p, precision=prec, out=outs[1], workspace=ws[1])
         return step, ws
 
-    results = {}
-    for prec in (q2x.FP32_MIXED, q2x.FP64):
-        step, ws = make_step(prec)
+    def timed(prec, fused, steps):
+        step, ws = make_step(prec, fused)
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
@@ -79,23 +87,31 @@ def main():
         q2x.profile_reset()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             step()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         rec_ms, call_ms, calls = q2x.profile_read()
         q2x.profile_enable(False)
-        flags = [q2x.status(ws[k])[0] for k in (0, 1)]
-        ms = (t1 - t0) * 1e3 / args.steps
-        coefs = 2 * N * (p + 1) ** 2
+        flags = [q2x.status(w)[0] for w in ws.values()]
+        ms = (t1 - t0) * 1e3 / steps
         per_kind = {}
-        for k in (0, 1):
+        for k in ws:
             avg = rec_ms[k] / max(calls[k], 1)
             fl = flops.launch_flops(k, p, N)
             per_kind[q2x.KIND_NAMES[k]] = {"recursion_kernel_ms": avg, "call_ms": call_ms[k] / max(calls[k], 1),
                                            "algorithmic_flops": fl, "tflops": fl / (avg * 1e-3) / 1e12}
-        results[prec] = {"ms_per_step": ms, "value": coefs / (ms * 1e-3), "per_kind": per_kind, "flags": flags,
-                         "single": coef_complex(outs[0]), "double": coef_complex(outs[1])}
+        return {"ms_per_step": ms, "value": coefs / (ms * 1e-3), "per_kind": per_kind, "flags": flags,
+                "single": coef_complex(outs[0]), "double": coef_complex(outs[1])}
+
+    coefs = 2 * N * (p + 1) ** 2
+    results, separate = {}, {}
+    for prec in (q2x.FP32_MIXED, q2x.FP64):
+        results[prec] = timed(prec, True, args.steps)
+        separate[prec] = timed(prec, False, max(args.steps // 2, 1))
+        for layer in ("single", "double"):  # the fused and separate paths give bitwise the same coefficients
+            if not np.array_equal(results[prec][layer], separate[prec][layer]):
+                raise SystemExit(f"fused and separate {layer}-layer results differ (precision {prec})")
 
     mixed, plain = results[q2x.FP32_MIXED], results[q2x.FP64]
     # agreement of the two GPU precisions (scale-free check; parity vs the oracle is in tests/)
@@ -122,6 +138,9 @@ def main():
                    "n_elements": N, "n_boxes": B, "p": p, "elements_per_step": 2 * N,
                    "coefficients_per_step": 2 * N * (p + 1) ** 2, "precision": "FP32-mixed"},
         "fp64_plain": {"value": plain["value"], "ms_per_step": plain["ms_per_step"], "per_kind": plain["per_kind"]},
+        "separate_calls": {"fp32_mixed_ms_per_step": separate[q2x.FP32_MIXED]["ms_per_step"],
+                           "fp64_ms_per_step": separate[q2x.FP64]["ms_per_step"],
+                           "per_kind_mixed": separate[q2x.FP32_MIXED]["per_kind"]},
         "speedup_mixed_vs_fp64": plain["ms_per_step"] / mixed["ms_per_step"],
         "per_kind_mixed": mixed["per_kind"],
         "mixed_vs_fp64_max_rel_diff": agree,

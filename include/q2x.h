@@ -70,7 +70,13 @@ typedef enum {
   Q2X_ERR_UNSUPPORTED = -5  /* valid request this build does not implement */
 } q2x_status;
 
-typedef enum { Q2X_TRI_SINGLE = 0, Q2X_TRI_DOUBLE = 1, Q2X_SEGMENT = 2, Q2X_TET = 3 } q2x_kind;
+typedef enum {
+  Q2X_TRI_SINGLE = 0,
+  Q2X_TRI_DOUBLE = 1,
+  Q2X_SEGMENT = 2,
+  Q2X_TET = 3,
+  Q2X_TRI_BOTH = 4 /* single + double layer of one triangle mesh (q2x_tri_both) */
+} q2x_kind;
 typedef enum { Q2X_FP64 = 0, Q2X_FP32_MIXED = 1 } q2x_precision;
 typedef enum { Q2X_NORM_FMM = 0, Q2X_NORM_MOMENT = 1 } q2x_norm;
 
@@ -121,6 +127,21 @@ q2x_status q2x_tri_double(const double* verts, int64_t n_verts, const int32_t* t
                           const double* box_radius, int64_t n_boxes, int p, int precision, int norm,
                           unsigned flags, double* coeffs, void* workspace, size_t workspace_bytes,
                           void* stream);
+
+/*
+ * Single AND double layer of the same triangles in one call: one bucketing
+ * and one recursion, since the double layer of degree n is D_nu applied to the
+ * single-layer surface integrals of degree n-1 (Sec. 3.4, Eqs. (53),(56)).
+ * Results equal q2x_tri_single(density_single) -> coeffs_single and
+ * q2x_tri_double(density_double) -> coeffs_double (same rounding, bitwise);
+ * the workspace is q2x_workspace_bytes(Q2X_TRI_BOTH, ...).  The two output
+ * arrays must not overlap.  Other arguments as for q2x_tri_single.
+ */
+q2x_status q2x_tri_both(const double* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+                        const double* density_single, const double* density_double, const int32_t* elem_box,
+                        const double* box_center, const double* box_radius, int64_t n_boxes, int p,
+                        int precision, int norm, unsigned flags, double* coeffs_single, double* coeffs_double,
+                        void* workspace, size_t workspace_bytes, void* stream);
 
 /*
  * Line segments with constant scalar line density (the integrals K of Sec. 2,
@@ -179,7 +200,7 @@ const char* q2x_status_string(int status);
  * Kernel timing for measurement.  When enabled, each call records HIP events
  * on its own stream around its recursion kernel and around the whole call;
  * q2x_profile_read synchronises those events and returns, per element kind
- * (arrays of 4 indexed by q2x_kind), the summed recursion-kernel time (ms),
+ * (arrays of 5 indexed by q2x_kind), the summed recursion-kernel time (ms),
  * the summed whole-call time (ms, bucketing and fix-up included) and the
  * number of calls since the last reset.  Any output pointer may be NULL.
  */

@@ -28,26 +28,32 @@ __global__ __launch_bounds__(256) void q2x_fixup_kernel(FixupArgs f) {
   const int ncoef = (f.p + 1) * (f.p + 1);
   const int nct_out = tri(f.p + 1);
   const int NCT = tri(f.P + 1);
+  const int64_t pstride = (int64_t)f.nout * NCT;  // partial sums per (tile, slot)
   for (int64_t b = wave; b < f.n_boxes; b += nwaves) {
     const int64_t s = f.n_pos ? f.box_start[b] : 0, t = f.n_pos ? f.box_start[b + 1] : 0;
-    double* row = f.coeffs + b * (int64_t)ncoef * 2;
     if (t <= s) {
       if (!f.accumulate)
-        for (int i = lane; i < 2 * ncoef; i += 64) row[i] = 0.0;
+        for (int o = 0; o < f.nout; ++o) {
+          double* row = (o ? f.coeffs2 : f.coeffs) + b * (int64_t)ncoef * 2;
+          for (int i = lane; i < 2 * ncoef; i += 64) row[i] = 0.0;
+        }
       continue;
     }
     const int64_t t0 = s / kTile, t1 = (t - 1) / kTile;
     if (t0 == t1) continue;  // finished by the tile kernel
-    for (int g = lane; g < nct_out; g += 64) {
+    for (int gg = lane; gg < f.nout * nct_out; gg += 64) {
+      const int o = gg / nct_out;
+      const int g = gg - o * nct_out;
       double ar = 0.0, ai = 0.0;
       for (int64_t tt = t0; tt <= t1; ++tt) {
         const int slot = (tt == t0 && s != t0 * kTile) ? 1 : 0;
-        const double* pp = f.partials + ((tt * 2 + slot) * (int64_t)NCT + g) * 2;
+        const double* pp = f.partials + ((tt * 2 + slot) * pstride + o * NCT + g) * 2;
         ar += pp[0];
         ai += pp[1];
       }
       int n, m;
       tri_nm(g, n, m);
+      double* row = (o ? f.coeffs2 : f.coeffs) + b * (int64_t)ncoef * 2;
       finalize_store(row, n, m, ar, ai, f.norm, f.accumulate);
     }
   }
@@ -62,7 +68,7 @@ struct Layout {
   size_t status, box_start, sort, partials, total;
 };
 
-Layout layout(int64_t n, int64_t nb, int P) {
+Layout layout(int64_t n, int64_t nb, int P, int nout) {
   Layout L;
   size_t off = 0;
   L.status = off;
@@ -73,18 +79,13 @@ Layout layout(int64_t n, int64_t nb, int P) {
   off += align_up(bucket_scratch_bytes(n, nb));
   L.partials = off;
   const int64_t ntiles = (n + kTile - 1) / kTile;
-  off += align_up((size_t)ntiles * 2 * (size_t)tri(P + 1) * 2 * sizeof(double));
+  off += align_up((size_t)ntiles * 2 * (size_t)nout * (size_t)tri(P + 1) * 2 * sizeof(double));
   L.total = off;
   return L;
 }
 
-int verts_per_kind(int kind) {
-  switch (kind) {
-    case Q2X_SEGMENT: return 2;
-    case Q2X_TET: return 4;
-    default: return 3;
-  }
-}
+constexpr int kKinds = 5;
+int outputs_per_kind(int kind) { return kind == Q2X_TRI_BOTH ? 2 : 1; }
 
 // ---- kernel timing (measurement aid)
 struct Prof {
@@ -118,9 +119,10 @@ Prof::Ev get_ev() {
 }
 
 q2x_status run(int kind, const double* verts, int64_t n_verts, const int32_t* elems, int64_t n_elems,
-               const double* density, const int32_t* elem_box, const double* box_center, const double* box_radius,
-               int64_t n_boxes, int p, int prec, int norm, unsigned flags, double* coeffs, void* workspace,
-               size_t workspace_bytes, void* stream) {
+               const double* density, const double* density2, const int32_t* elem_box, const double* box_center,
+               const double* box_radius, int64_t n_boxes, int p, int prec, int norm, unsigned flags,
+               double* coeffs, double* coeffs2, void* workspace, size_t workspace_bytes, void* stream) {
+  const int nout = outputs_per_kind(kind);
   if (p < 0 || p > Q2X_P_MAX) return Q2X_ERR_P_RANGE;
   if (n_verts < 0 || n_elems < 0 || n_boxes < 0 || n_elems >= ((int64_t)1 << 31) - 64 ||
       n_boxes >= ((int64_t)1 << 31) - 1 || n_verts >= ((int64_t)1 << 31))
@@ -136,9 +138,18 @@ q2x_status run(int kind, const double* verts, int64_t n_verts, const int32_t* el
       ((uintptr_t)box_center % 8) || ((uintptr_t)elems % 4) ||
       ((uintptr_t)elem_box % 4))
     return Q2X_ERR_ARG;
+  if (nout == 2) {
+    if (n_boxes > 0 && !coeffs2) return Q2X_ERR_ARG;
+    if (n_elems > 0 && !density2) return Q2X_ERR_ARG;
+    if (((uintptr_t)coeffs2 % 8) || ((uintptr_t)density2 % 8)) return Q2X_ERR_ARG;
+    // the two outputs must not overlap
+    const size_t out_bytes = (size_t)n_boxes * (size_t)(p + 1) * (size_t)(p + 1) * 2 * sizeof(double);
+    const uintptr_t c1 = (uintptr_t)coeffs, c2 = (uintptr_t)coeffs2;
+    if (n_boxes > 0 && c1 < c2 + out_bytes && c2 < c1 + out_bytes) return Q2X_ERR_ARG;
+  }
   const int P = bucket_order(p);
   if (P < 0) return Q2X_ERR_UNSUPPORTED;
-  const Layout L = layout(n_elems, n_boxes, P);
+  const Layout L = layout(n_elems, n_boxes, P, nout);
   if (workspace_bytes < L.total) return Q2X_ERR_WORKSPACE;
 
   hipStream_t s = (hipStream_t)stream;
@@ -174,11 +185,13 @@ q2x_status run(int kind, const double* verts, int64_t n_verts, const int32_t* el
   a.verts = verts;
   a.elems = elems;
   a.density = density;
+  a.density2 = (nout == 2) ? density2 : nullptr;
   a.keys = keys;
   a.perm = perm;
   a.box_center = box_center;
   a.box_start = box_start;
   a.coeffs = coeffs;
+  a.coeffs2 = (nout == 2) ? coeffs2 : nullptr;
   a.partials = partials;
   a.status = st;
   a.n_verts = n_verts;
@@ -200,9 +213,11 @@ q2x_status run(int kind, const double* verts, int64_t n_verts, const int32_t* el
     f.partials = partials;
     f.n_pos = n_elems;
     f.coeffs = coeffs;
+    f.coeffs2 = a.coeffs2;
     f.n_boxes = n_boxes;
     f.p = p;
     f.P = P;
+    f.nout = nout;
     f.norm = norm;
     f.accumulate = a.accumulate;
     const int64_t waves = n_boxes;
@@ -228,11 +243,11 @@ using namespace q2x;
 extern "C" {
 
 size_t q2x_workspace_bytes(int kind, int64_t n_elems, int64_t n_boxes, int p, int precision) {
-  if (kind < 0 || kind > 3 || n_elems < 0 || n_boxes < 0 || p < 0 || p > Q2X_P_MAX) return 0;
+  if (kind < 0 || kind >= kKinds || n_elems < 0 || n_boxes < 0 || p < 0 || p > Q2X_P_MAX) return 0;
   if (precision != Q2X_FP64 && precision != Q2X_FP32_MIXED) return 0;
   const int P = bucket_order(p);
   if (P < 0) return 0;
-  return layout(n_elems, n_boxes, P).total;
+  return layout(n_elems, n_boxes, P, outputs_per_kind(kind)).total;
 }
 
 #define Q2X_ENTRY(name, KIND)                                                                                      \
@@ -240,14 +255,24 @@ size_t q2x_workspace_bytes(int kind, int64_t n_elems, int64_t n_boxes, int p, in
                   const int32_t* elem_box, const double* box_center, const double* box_radius, int64_t n_boxes,  \
                   int p, int precision, int norm, unsigned flags, double* coeffs, void* workspace,                \
                   size_t workspace_bytes, void* stream) {                                                         \
-    return run(KIND, verts, n_verts, el, n_el, density, elem_box, box_center, box_radius, n_boxes, p, precision,  \
-               norm, flags, coeffs, workspace, workspace_bytes, stream);                                          \
+    return run(KIND, verts, n_verts, el, n_el, density, nullptr, elem_box, box_center, box_radius, n_boxes, p,    \
+               precision, norm, flags, coeffs, nullptr, workspace, workspace_bytes, stream);                      \
   }
 
 Q2X_ENTRY(q2x_tri_single, Q2X_TRI_SINGLE)
 Q2X_ENTRY(q2x_tri_double, Q2X_TRI_DOUBLE)
 Q2X_ENTRY(q2x_segment, Q2X_SEGMENT)
 Q2X_ENTRY(q2x_tet, Q2X_TET)
+
+q2x_status q2x_tri_both(const double* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+                        const double* density_single, const double* density_double, const int32_t* elem_box,
+                        const double* box_center, const double* box_radius, int64_t n_boxes, int p,
+                        int precision, int norm, unsigned flags, double* coeffs_single, double* coeffs_double,
+                        void* workspace, size_t workspace_bytes, void* stream) {
+  return run(Q2X_TRI_BOTH, verts, n_verts, tris, n_tris, density_single, density_double, elem_box, box_center,
+             box_radius, n_boxes, p, precision, norm, flags, coeffs_single, coeffs_double, workspace,
+             workspace_bytes, stream);
+}
 
 size_t q2x_bucket_workspace_bytes(int64_t n_elems, int64_t n_boxes) {
   if (n_elems < 0 || n_boxes < 0) return 0;
@@ -318,8 +343,8 @@ void q2x_profile_reset(void) {
 q2x_status q2x_profile_read(double* recursion_ms, double* call_ms, int64_t* calls) {
   Prof& P = prof();
   std::lock_guard<std::mutex> g(P.mu);
-  double rec[4] = {0, 0, 0, 0}, tot[4] = {0, 0, 0, 0};
-  int64_t cnt[4] = {0, 0, 0, 0};
+  double rec[kKinds] = {}, tot[kKinds] = {};
+  int64_t cnt[kKinds] = {};
   for (auto& e : P.evs) {
     if (hipEventSynchronize(e.d) != hipSuccess) return Q2X_ERR_HIP;
     float a = 0.f, b = 0.f;
@@ -329,7 +354,7 @@ q2x_status q2x_profile_read(double* recursion_ms, double* call_ms, int64_t* call
     tot[e.kind] += b;
     cnt[e.kind] += 1;
   }
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < kKinds; ++k) {
     if (recursion_ms) recursion_ms[k] = rec[k];
     if (call_ms) call_ms[k] = tot[k];
     if (calls) calls[k] = cnt[k];

@@ -31,12 +31,14 @@ struct TileArgs {
   const double* verts;
   const int32_t* elems;
   const double* density;
+  const double* density2;    // second output's density (two-output kinds), else nullptr
   const int32_t* keys;       // box id of each sorted position (elem_box itself when presorted)
   const int32_t* perm;       // sorted position -> element index (nullptr: identity)
   const double* box_center;
   int32_t* box_start;        // [n_boxes + 1] out: start position of each box
   double* coeffs;            // [n_boxes][(p+1)^2][2]
-  double* partials;          // [n_tiles][2][tri(P+1)][2] raw sums of boxes cut by tile edges
+  double* coeffs2;           // second output (two-output kinds), else nullptr
+  double* partials;          // [n_tiles][2][nout][tri(P+1)][2] raw sums of boxes cut by tile edges
   Status* status;
   int64_t n_verts;
   int64_t n_pos;             // number of positions covered by tiles (= n_elems)
@@ -51,10 +53,12 @@ struct FixupArgs {
   const int32_t* box_start;  // written by the tile kernel (unused when n_pos == 0)
   const double* partials;
   double* coeffs;
+  double* coeffs2;
   int64_t n_pos;
   int64_t n_boxes;
   int p;
   int P;                     // bucket order the partials were laid out for
+  int nout;                  // outputs per element kind (1, or 2 for Q2X_TRI_BOTH)
   int norm;
   int accumulate;
 };

@@ -2,7 +2,7 @@
 // tile of 64 box-sorted elements, one lane per element).
 //
 // Per lane: FP64 geometry of its element relative to its box centre, then the
-// m >= 0 ("tilde") recursions of Sec. 3.4, Eqs. (50)-(55), degree by degree,
+// m >= 0 ("tilde") recursions of Sec. 3.4, Eqs. (50)-(56), degree by degree,
 // with the whole recursion state in VGPRs (template order P, fully unrolled).
 // The recursion carries G_n = (n+k)! t~_n (k = nesting depth), which removes
 // every division from Eqs. (50)-(55) and keeps the values O(1) at any order.
@@ -10,10 +10,12 @@
 // distance from c, so nothing underflows whatever the element's size and
 // position (degree n of the result scales as a_e^n); the FP64 path runs on
 // x - c unscaled.
+// An element kind has one output (single layer, double layer, segment, tet)
+// or two (single and double layer of one triangle mesh from one recursion).
 // Every degree's outputs go to an LDS stage (real and imaginary parts in
-// separate rows), and the FP64 factor s_e a_e^n / (n+k)!
+// separate rows), and the FP64 factors s_e a_e^n / (n+k)!
 // (s_e = sigma_e J_e / 4pi) to a small table beside it.  When a group of
-// degrees ("chunk", <= CMAX coefficients) is complete the wavefront transposes
+// outputs ("chunk", <= CMAX coefficients) is complete the wavefront transposes
 // through LDS -- lane = coefficient -- and walks the 64 elements in order, one
 // box segment at a time, summing factor * value in FP64.  Boxes wholly inside
 // the tile are finalised and stored directly; a box cut by a tile edge leaves
@@ -110,26 +112,32 @@ __device__ __forceinline__ void ladder(CArr<T, P1>& out, const CArr<T, P1>& F, c
   });
 }
 
-// Greedy grouping of degrees 0..P into chunks of at most CMAX tilde
-// coefficients (degree n has n+1 of them).
-template <int P, int CMAX>
+// Greedy grouping of the staged outputs into chunks of at most CMAX
+// coefficients.  The unit of grouping is one output of one degree (n + 1
+// coefficients): unit u = NOUT n + s holds degree n, slot s, in the order the
+// recursion produces them, so a chunk may end between the outputs of a degree.
+template <int P, int CMAX, int NOUT>
 struct ChunkPlan {
-  static constexpr int first_level(int n) {
+  static constexpr int U = NOUT * (P + 1);  // number of units
+  static constexpr int level(int u) { return u / NOUT; }
+  static constexpr int size(int u) { return u / NOUT + 1; }
+  static constexpr int off(int u) { return NOUT * tri(u / NOUT) + (u % NOUT) * (u / NOUT + 1); }
+  static constexpr int first_unit(int u) {
     int s = 0;
-    for (int l = 0; l <= n; ++l)
-      if (tri(l + 1) - tri(s) > CMAX) s = l;
+    for (int l = 0; l <= u; ++l)
+      if (off(l + 1) - off(s) > CMAX) s = l;
     return s;
   }
-  static constexpr bool is_end(int n) { return n == P || first_level(n + 1) == n + 1; }
-  static constexpr int end_of(int n) {
-    int e = n;
+  static constexpr bool is_end(int u) { return u == U - 1 || first_unit(u + 1) == u + 1; }
+  static constexpr int end_of(int u) {
+    int e = u;
     while (!is_end(e)) ++e;
     return e;
   }
-  static constexpr int max_degrees() {
+  static constexpr int max_units() {
     int mx = 0;
-    for (int n = 0; n <= P; ++n) {
-      const int d = n - first_level(n) + 1;
+    for (int u = 0; u < U; ++u) {
+      const int d = u - first_unit(u) + 1;
       if (d > mx) mx = d;
     }
     return mx;
@@ -137,31 +145,56 @@ struct ChunkPlan {
 };
 
 // The recursion chain of each element kind (Sec. 3.4): array k of the chain is
-// laddered about vertex vert(k) and fed by array k-1; the output is the last
-// array (for the double layer: D_nu of the last array one degree lower).
-//   nv: vertices; shift: degree n of the output scales as a^(n - shift);
-//   depth: the output at degree n is G / (n + depth)!.
+// laddered about vertex vert(k) and fed by array k-1.  Output o of degree n is
+// the chain's last array (double layer: D_nu of it one degree lower, Eq. (56));
+// it scales as a^(n - shift(o)), carries G / (n + depth(o))! and is staged in
+// slot slot(o) of its degree (the order the recursion produces the outputs).
 template <int KIND>
 struct KindInfo;
 template <>
 struct KindInfo<Q2X_TRI_SINGLE> {  // q at x2, j along x3->x2, i from x1 (Eqs. (50)-(53))
-  static constexpr int nv = 3, shift = 0, depth = 2, nch = 3;
+  static constexpr int nv = 3, nch = 3, nout = 1;
   static constexpr int vert(int k) { return k == 0 ? 1 : (k == 1 ? 2 : 0); }
+  static constexpr bool dbl(int) { return false; }
+  static constexpr int shift(int) { return 0; }
+  static constexpr int depth(int) { return 2; }
+  static constexpr int slot(int) { return 0; }
 };
 template <>
 struct KindInfo<Q2X_TRI_DOUBLE> {  // the same chain; output Eq. (56)
-  static constexpr int nv = 3, shift = 1, depth = 1, nch = 3;
+  static constexpr int nv = 3, nch = 3, nout = 1;
   static constexpr int vert(int k) { return k == 0 ? 1 : (k == 1 ? 2 : 0); }
+  static constexpr bool dbl(int) { return true; }
+  static constexpr int shift(int) { return 1; }
+  static constexpr int depth(int) { return 1; }
+  static constexpr int slot(int) { return 0; }
 };
 template <>
 struct KindInfo<Q2X_SEGMENT> {  // q at x2, p from x1 (Eqs. (50)-(51))
-  static constexpr int nv = 2, shift = 0, depth = 1, nch = 2;
+  static constexpr int nv = 2, nch = 2, nout = 1;
   static constexpr int vert(int k) { return k == 0 ? 1 : 0; }
+  static constexpr bool dbl(int) { return false; }
+  static constexpr int shift(int) { return 0; }
+  static constexpr int depth(int) { return 1; }
+  static constexpr int slot(int) { return 0; }
 };
 template <>
 struct KindInfo<Q2X_TET> {  // q at x2, j along x3->x2, b from x4, a from x1 (Eqs. (54)-(55))
-  static constexpr int nv = 4, shift = 0, depth = 3, nch = 4;
+  static constexpr int nv = 4, nch = 4, nout = 1;
   static constexpr int vert(int k) { return k == 0 ? 1 : (k == 1 ? 2 : (k == 2 ? 3 : 0)); }
+  static constexpr bool dbl(int) { return false; }
+  static constexpr int shift(int) { return 0; }
+  static constexpr int depth(int) { return 3; }
+  static constexpr int slot(int) { return 0; }
+};
+template <>
+struct KindInfo<Q2X_TRI_BOTH> {  // output 0 single layer, output 1 double layer, one chain
+  static constexpr int nv = 3, nch = 3, nout = 2;
+  static constexpr int vert(int k) { return k == 0 ? 1 : (k == 1 ? 2 : 0); }
+  static constexpr bool dbl(int o) { return o == 1; }
+  static constexpr int shift(int o) { return o == 1 ? 1 : 0; }
+  static constexpr int depth(int o) { return o == 1 ? 1 : 2; }
+  static constexpr int slot(int o) { return o == 1 ? 0 : 1; }  // l~_n (from degree n-1) before i~_n
 };
 
 template <typename T>
@@ -179,25 +212,26 @@ struct PrecInfo<double> {
   static constexpr int cmax = 32;
 };
 
+constexpr double inv_fact(int k) { return k <= 1 ? 1.0 : (k == 2 ? 0.5 : (k == 3 ? 1.0 / 6.0 : 1.0 / 24.0)); }
+
 template <int P, int KIND, typename T>
 __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_tiles) {
   using KI = KindInfo<KIND>;
   constexpr int P1 = P + 1;
   constexpr int NV = KI::nv;
   constexpr int NCH = KI::nch;
-  constexpr int SHIFT = KI::shift;
-  constexpr int DEPTH = KI::depth;
+  constexpr int NOUT = KI::nout;
   constexpr int CMAX = (PrecInfo<T>::cmax > P + 1) ? PrecInfo<T>::cmax : P + 1;
   constexpr int SSTR = kTile + 1;  // padded row stride (elements) of the stage and factor tables
   constexpr int NCT = tri(P + 1);
   constexpr bool SCALED = PrecInfo<T>::scaled;
-  using Plan = ChunkPlan<P, CMAX>;
-  constexpr int DMAX = Plan::max_degrees();
+  using Plan = ChunkPlan<P, CMAX, NOUT>;
+  constexpr int DMAX = Plan::max_units();
 
   // stage: real part of chunk coefficient c in row c, imaginary part in row CMAX + c
   __shared__ T stage[2 * CMAX * SSTR];
-  __shared__ double fac[DMAX * SSTR];
-  __shared__ int tkey[kTile];  // box id of every element of the tile
+  __shared__ double fac[DMAX * SSTR];         // row u - U0 (unit u of a chunk starting at unit U0)
+  __shared__ int tkey[kTile];                 // box id of every element of the tile
 
   const int64_t tile = xcd_tile(blockIdx.x, n_tiles);
   const int lane = threadIdx.x;
@@ -217,7 +251,10 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
   double xv[NV][3];
 #pragma unroll
   for (int k = 0; k < NV; ++k) xv[k][0] = xv[k][1] = xv[k][2] = 0.0;
-  double sigma = 0.0, cx = 0.0, cy = 0.0, cz = 0.0;
+  double sigma[NOUT];
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) sigma[o] = 0.0;
+  double cx = 0.0, cy = 0.0, cz = 0.0;
   if (ok) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
@@ -231,13 +268,16 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
         xv[k][2] = a.verts[3 * (int64_t)vi + 2];
       }
     }
-    sigma = a.density[e];
+    sigma[0] = a.density[e];
+    if constexpr (NOUT == 2) sigma[1] = a.density2[e];
     cx = a.box_center[3 * (int64_t)key];
     cy = a.box_center[3 * (int64_t)key + 1];
     cz = a.box_center[3 * (int64_t)key + 2];
   }
   if (ok) {
-    bool fin = isfinite(sigma) && isfinite(cx) && isfinite(cy) && isfinite(cz);
+    bool fin = isfinite(cx) && isfinite(cy) && isfinite(cz);
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) fin = fin && isfinite(sigma[o]);
 #pragma unroll
     for (int k = 0; k < NV; ++k) fin = fin && isfinite(xv[k][0]) && isfinite(xv[k][1]) && isfinite(xv[k][2]);
     if (!fin) {
@@ -269,8 +309,6 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
     }
   }
   const bool degenerate = ok && !(J > 0.0);
-  // weight s_e = sigma J / (4 pi) (Sec. 3.2, Eq. (20)); skipped elements weigh 0
-  const double w64 = ok ? sigma * J * kInv4Pi : 0.0;
 
   // element scale a_e (FP32 path) and the recursion's vertex data
   double X[NV][3];
@@ -297,9 +335,14 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
     vxr2[k] = (T)(X[k][0] * inv_scl);
     vxi2[k] = (T)(X[k][1] * inv_scl);
   }
-  // running FP64 factor s_e a_e^(n - SHIFT) / (n + DEPTH)! of the degree being produced
-  constexpr double inv_depth_fact = (DEPTH == 1) ? 1.0 : (DEPTH == 2) ? 0.5 : 1.0 / 6.0;
-  double fpow = ((SHIFT == 1) ? w64 * inv_scl : w64) * inv_depth_fact;
+  // running FP64 factors s_e a_e^(n - shift) / (n + depth)! of the degree being
+  // produced; s_e = sigma_e J / (4 pi) (Sec. 3.2, Eq. (20)), 0 for skipped elements
+  double fpow[NOUT];
+  static_for<0, NOUT>([&](auto OO) {
+    constexpr int o = decltype(OO)::value;
+    const double w64 = ok ? sigma[o] * J * kInv4Pi : 0.0;
+    fpow[o] = ((KI::shift(o) == 1) ? w64 * inv_scl : w64) * inv_fact(KI::depth(o));
+  });
 
   // ---- box start table: box_start[b] = first position whose key >= b, keys
   // outside [0, B) counting as -1 / B (the fix-up kernel reads it)
@@ -338,31 +381,30 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
   const int p = a.p;
   const int ncoef_out = (p + 1) * (p + 1);
 
-  // ---- reduction of one chunk of degrees [L0, L1]
+  // ---- reduction of one chunk of units [U0, U1]
   // lane = (group g, coefficient c): with CMAX <= 32 the two half-waves walk
   // elements [0,32) and [32,64) of the same coefficient (G = 2), otherwise one
   // lane walks all 64 (G = 1).  Within a group every box segment is summed in
   // element order and flushed where it ends; the one segment that may straddle
   // the halves is summed by both and joined (tail of half 0 + head of half 1).
-  auto flush = [&](int sa, int sb, double accr, double acci, bool wr, int n, int m, int g_coef) {
+  auto flush = [&](int sa, int sb, double accr, double acci, bool wr, int n, int m, double* out, int g_coef) {
     const int box = tkey[sa];  // (an LDS table: flushes run in lane-divergent code)
     if (!(wr && box >= 0 && box < a.n_boxes)) return;
     const bool open = (sa == 0 && head_open) || (sb == kTile && tail_open);
     if (open) {
       const int slot = (sa == 0) ? 0 : 1;
-      double* pp = a.partials + ((tile * 2 + slot) * (int64_t)NCT + g_coef) * 2;
+      double* pp = a.partials + ((tile * 2 + slot) * (int64_t)(NOUT * NCT) + g_coef) * 2;
       pp[0] = accr;
       pp[1] = acci;
     } else {
-      finalize_store(a.coeffs + (int64_t)box * ncoef_out * 2, n, m, accr, acci, a.norm, a.accumulate);
+      finalize_store(out + (int64_t)box * ncoef_out * 2, n, m, accr, acci, a.norm, a.accumulate);
     }
   };
-  auto reduce_chunk = [&](auto L0c, auto L1c) {
-    constexpr int L0 = decltype(L0c)::value;
-    constexpr int L1 = decltype(L1c)::value;
-    constexpr int CB = tri(L0);
-    constexpr int C = tri(L1 + 1) - tri(L0);
-    static_assert(C <= CMAX && L1 - L0 + 1 <= DMAX, "chunk too large");
+  auto reduce_chunk = [&](auto U0c, auto U1c) {
+    constexpr int U0 = decltype(U0c)::value;
+    constexpr int U1 = decltype(U1c)::value;
+    constexpr int C = Plan::off(U1 + 1) - Plan::off(U0);
+    static_assert(C <= CMAX && U1 - U0 + 1 <= DMAX, "chunk too large");
     constexpr int G = (CMAX <= 32) ? 2 : 1;
     constexpr int E = kTile / G;
     __syncthreads();
@@ -370,12 +412,24 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
     const int c = (G == 2) ? (lane & 31) : lane;
     const bool act = c < C;
     const int cc = act ? c : 0;
-    int n = 0, m = 0;
-    tri_nm(CB + cc, n, m);
+    // decode chunk coefficient cc -> unit u (degree n, output o), order m
+    int u = U0, r = cc;
+    static_for<U0, U1>([&](auto UU) {
+      constexpr int l = decltype(UU)::value;
+      if (u == l && r >= Plan::size(l)) {
+        r -= Plan::size(l);
+        u = l + 1;
+      }
+    });
+    const int n = u / NOUT;
+    const int o = (NOUT == 1) ? 0 : ((u % NOUT) == KI::slot(0) ? 0 : 1);
+    const int m = r;
     const bool wr = act && n <= p;
+    double* out = (o == 0) ? a.coeffs : a.coeffs2;
+    const int g_coef = o * NCT + tri(n) + m;
     const T* rre = stage + cc * SSTR;
     const T* rim = stage + (CMAX + cc) * SSTR;
-    const double* frow = fac + (n - L0) * SSTR;
+    const double* frow = fac + (u - U0) * SSTR;
     const int gs = g * E;
     const int ge = min(gs + E, ne);
     const bool cont_in = (g > 0) && (gs < ne) && !((bnd >> gs) & 1ull);
@@ -409,7 +463,7 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
           head_end = el;
           in_head = false;
         } else {
-          flush(seg, el, accr, acci, wr, n, m, CB + c);
+          flush(seg, el, accr, acci, wr, n, m, out, g_coef);
         }
         accr = 0.0;
         acci = 0.0;
@@ -425,7 +479,7 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
         hi = acci;
         head_end = ge;
       } else if (!cont_out) {
-        flush(seg, ge, accr, acci, wr, n, m, CB + c);
+        flush(seg, ge, accr, acci, wr, n, m, out, g_coef);
       }
     }
     if constexpr (G == 2) {
@@ -433,29 +487,32 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
       const double jr = __shfl(hr, lane + 32);
       const double ji = __shfl(hi, lane + 32);
       const int jend = __shfl(head_end, lane + 32);
-      if (cont_out) flush(seg, jend, accr + jr, acci + ji, wr, n, m, CB + c);
+      if (cont_out) flush(seg, jend, accr + jr, acci + ji, wr, n, m, out, g_coef);
     }
     __syncthreads();
   };
 
-  // stage degree N's outputs and its FP64 factor; reduce at chunk ends (and at
-  // the requested order when it falls inside a chunk)
-  auto put_level = [&](auto NNc, const CArr<T, P1>& V) {
+  // output o of degree N: stage it and its FP64 factors; reduce at chunk ends
+  // (and after the last output of the requested order when that falls inside
+  // a chunk)
+  auto emit = [&](auto NNc, auto OO, const CArr<T, P1>& V) {
     constexpr int N = decltype(NNc)::value;
-    constexpr int L0 = Plan::first_level(N);
+    constexpr int o = decltype(OO)::value;
+    constexpr int u = NOUT * N + KI::slot(o);
+    constexpr int U0 = Plan::first_unit(u);
+    constexpr int row0 = Plan::off(u) - Plan::off(U0);
     static_for<0, N + 1>([&](auto MM) {
       constexpr int m = decltype(MM)::value;
-      constexpr int row = tri(N) - tri(L0) + m;
-      stage[row * SSTR + lane] = V.r[m];
-      stage[(CMAX + row) * SSTR + lane] = V.i[m];
+      stage[(row0 + m) * SSTR + lane] = V.r[m];
+      stage[(CMAX + row0 + m) * SSTR + lane] = V.i[m];
     });
-    fac[(N - L0) * SSTR + lane] = fpow;
-    constexpr double inv_next = 1.0 / (double)(N + 1 + DEPTH);
-    fpow = fpow * scl * inv_next;
-    if constexpr (Plan::is_end(N)) {
-      reduce_chunk(IC<L0>{}, IC<N>{});
-    } else if (N == p) {
-      reduce_chunk(IC<L0>{}, IC<Plan::end_of(N)>{});
+    fac[(u - U0) * SSTR + lane] = fpow[o];
+    constexpr double inv_next = 1.0 / (double)(N + 1 + KI::depth(o));
+    fpow[o] = fpow[o] * scl * inv_next;
+    if constexpr (Plan::is_end(u)) {
+      reduce_chunk(IC<U0>{}, IC<u>{});
+    } else if (KI::slot(o) == NOUT - 1 && N == p) {
+      reduce_chunk(IC<U0>{}, IC<Plan::end_of(u)>{});
     }
   };
 
@@ -480,11 +537,12 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
     S0[k].r[0] = T(1);
     S0[k].i[0] = T(0);
   }
-  if constexpr (KIND != Q2X_TRI_DOUBLE) {
-    // S holds degree N; stage the chain's last array
+  constexpr bool HAS_DBL = KI::dbl(NOUT - 1);
+  if constexpr (!HAS_DBL) {
+    // S holds degree N; emit the chain's last array
     auto rec = [&](auto self, auto NNc, const CArr<T, P1>(&S)[NCH]) -> void {
       constexpr int N = decltype(NNc)::value;
-      put_level(IC<N>{}, S[NCH - 1]);
+      emit(IC<N>{}, IC<0>{}, S[NCH - 1]);
       if constexpr (N < P) {
         if (N < p) {
           CArr<T, P1> nS[NCH];
@@ -495,8 +553,10 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
     };
     rec(rec, IC<0>{}, S0);
   } else {
-    // double layer: l~_N = D_nu i~_{N-1}, nu = (n_x + i n_y)/2 (Sec. 3.4, Eq. (56));
-    // S holds degree max(N-1, 0)
+    // double layer (output NOUT-1): l~_N = D_nu i~_{N-1}, nu = (n_x + i n_y)/2
+    // (Sec. 3.4, Eq. (56)); with two outputs the single layer (output 0) is i~_N.
+    // S holds degree max(N-1, 0).
+    constexpr int OD = NOUT - 1;
     const T hnx = (T)(0.5 * nx), hny = (T)(0.5 * ny), tnz = (T)nz, nx2 = (T)nx, ny2 = (T)ny;
     auto rec = [&](auto self, auto NNc, const CArr<T, P1>(&S)[NCH]) -> void {
       constexpr int N = decltype(NNc)::value;
@@ -504,13 +564,23 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
         CArr<T, P1> Z;
         Z.r[0] = T(0);
         Z.i[0] = T(0);
-        put_level(IC<0>{}, Z);
+        emit(IC<0>{}, IC<OD>{}, Z);
+        if constexpr (NOUT == 2) emit(IC<0>{}, IC<0>{}, S[NCH - 1]);
         if (0 < p) self(self, IC<1>{}, S);
       } else {
-        CArr<T, P1> L;
-        ladder<N, false>(L, S[NCH - 1], S[NCH - 1], hnx, hny, tnz, nx2, ny2);
-        put_level(IC<N>{}, L);
-        if constexpr (N < P) {
+        {
+          CArr<T, P1> L;
+          ladder<N, false>(L, S[NCH - 1], S[NCH - 1], hnx, hny, tnz, nx2, ny2);
+          emit(IC<N>{}, IC<OD>{}, L);
+        }
+        if constexpr (NOUT == 2) {
+          CArr<T, P1> nS[NCH];
+          advance(IC<N>{}, nS, S);
+          emit(IC<N>{}, IC<0>{}, nS[NCH - 1]);
+          if constexpr (N < P) {
+            if (N < p) self(self, IC<N + 1>{}, nS);
+          }
+        } else if constexpr (N < P) {
           if (N < p) {
             CArr<T, P1> nS[NCH];
             advance(IC<N>{}, nS, S);

@@ -11,7 +11,8 @@ Eqs. (50)-(56), is evaluated in the m >= 0 form with zero padding pruned
   recursions) 2 FLOPs (1 at m = 0).
   Per degree:  triangle single = q + j(+q) + i(+j);  segment = q + p(+q);
   tetrahedron = q + j + b + a;  double layer = one D_nu step on i_{n-1}
-  (no source) plus the q, j, i steps to degree n-1.
+  (no source) plus the q, j, i steps to degree n-1; single + double of one
+  mesh (one recursion) = the D_nu step plus the q, j, i steps to degree n.
   The recursion runs on G_n = (n+k)! t_n, so it has no per-step constants;
   the FP64 factor s_e a_e^n/(n+k)! costs 2 multiplies per degree, and the
   reduction one FP64 FMA per real component of every element-coefficient
@@ -23,8 +24,9 @@ box coefficients written, B_occ (p+1)^2 16 B.
 """
 from __future__ import annotations
 
-TRI_SINGLE, TRI_DOUBLE, SEGMENT, TET = 0, 1, 2, 3
-NV = {TRI_SINGLE: 3, TRI_DOUBLE: 3, SEGMENT: 2, TET: 4}
+TRI_SINGLE, TRI_DOUBLE, SEGMENT, TET, TRI_BOTH = 0, 1, 2, 3, 4
+NV = {TRI_SINGLE: 3, TRI_DOUBLE: 3, SEGMENT: 2, TET: 4, TRI_BOTH: 3}
+NOUT = {TRI_SINGLE: 1, TRI_DOUBLE: 1, SEGMENT: 1, TET: 1, TRI_BOTH: 2}
 GEOMETRY_FLOPS = 60
 
 
@@ -65,6 +67,10 @@ def recursion_flops(kind: int, p: int) -> int:
             f += ladder_flops(n, False)  # l_n = D_nu i_{n-1}
             if n < p:
                 f += ladder_flops(n, False) + 2 * ladder_flops(n, True)
+    elif kind == TRI_BOTH:
+        for n in range(1, p + 1):
+            f += ladder_flops(n, False)  # l_n = D_nu i_{n-1}
+            f += ladder_flops(n, False) + 2 * ladder_flops(n, True)
     else:
         raise ValueError(kind)
     return f
@@ -73,7 +79,7 @@ def recursion_flops(kind: int, p: int) -> int:
 def element_flops(kind: int, p: int) -> int:
     """Total FLOPs per element: geometry + recursion + factors + reduction."""
     nct = (p + 1) * (p + 2) // 2
-    return GEOMETRY_FLOPS + recursion_flops(kind, p) + 2 * (p + 1) + 4 * nct
+    return GEOMETRY_FLOPS + recursion_flops(kind, p) + NOUT[kind] * (2 * (p + 1) + 4 * nct)
 
 
 def launch_flops(kind: int, p: int, n_elems: int) -> int:
@@ -81,8 +87,8 @@ def launch_flops(kind: int, p: int, n_elems: int) -> int:
 
 
 def launch_bytes(kind: int, p: int, n_elems: int, n_boxes_occupied: int) -> int:
-    per_elem = 4 * NV[kind] + 8 + 4 + 4 + 24 * NV[kind]  # indices, density, box id, perm, vertices
-    return per_elem * n_elems + 16 * (p + 1) ** 2 * n_boxes_occupied
+    per_elem = 4 * NV[kind] + 8 * NOUT[kind] + 4 + 4 + 24 * NV[kind]  # indices, densities, box id, perm, vertices
+    return per_elem * n_elems + NOUT[kind] * 16 * (p + 1) ** 2 * n_boxes_occupied
 
 
 # MI355X vector-ALU peak.  256 CUs x 4 SIMDs x 16 lanes = 4096 FMA lanes per
@@ -97,5 +103,5 @@ PEAK_HBM_GBS = 8000.0
 
 
 if __name__ == "__main__":
-    for k, name in ((0, "tri_single"), (1, "tri_double"), (2, "segment"), (3, "tet")):
+    for k, name in ((0, "tri_single"), (1, "tri_double"), (2, "segment"), (3, "tet"), (4, "tri_both")):
         print(name, [recursion_flops(k, p) for p in (8, 12, 16, 20, 24)], [element_flops(k, p) for p in (8, 12, 16, 20, 24)])

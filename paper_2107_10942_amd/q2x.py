@@ -14,16 +14,18 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libq2x.so")
 
-TRI_SINGLE, TRI_DOUBLE, SEGMENT, TET = 0, 1, 2, 3
-KIND_NAMES = {TRI_SINGLE: "tri_single", TRI_DOUBLE: "tri_double", SEGMENT: "segment", TET: "tet"}
-VERTS_PER_KIND = {TRI_SINGLE: 3, TRI_DOUBLE: 3, SEGMENT: 2, TET: 4}
+TRI_SINGLE, TRI_DOUBLE, SEGMENT, TET, TRI_BOTH = 0, 1, 2, 3, 4
+N_KINDS = 5
+KIND_NAMES = {TRI_SINGLE: "tri_single", TRI_DOUBLE: "tri_double", SEGMENT: "segment", TET: "tet",
+              TRI_BOTH: "tri_both"}
+VERTS_PER_KIND = {TRI_SINGLE: 3, TRI_DOUBLE: 3, SEGMENT: 2, TET: 4, TRI_BOTH: 3}
 FP64, FP32_MIXED = 0, 1
 NORM_FMM, NORM_MOMENT = 0, 1
 ACCUMULATE, PRESORTED = 1, 2
 P_MAX = 32
 FLAG_BAD_BOX, FLAG_NONFINITE, FLAG_RESERVED, FLAG_BAD_VERTEX, FLAG_NOT_SORTED = 1, 2, 4, 8, 16
 EXPORTS = ("q2x_workspace_bytes", "q2x_bucket_workspace_bytes", "q2x_bucket", "q2x_tri_single", "q2x_tri_double", "q2x_segment", "q2x_tet",
-           "q2x_status_get", "q2x_status_string", "q2x_profile_enable", "q2x_profile_reset",
+           "q2x_tri_both", "q2x_status_get", "q2x_status_string", "q2x_profile_enable", "q2x_profile_reset",
            "q2x_profile_read", "q2x_version")
 
 
@@ -48,6 +50,8 @@ def lib():
             f = getattr(L, name)
             f.argtypes = [vp, i64, vp, i64, vp, vp, vp, vp, i64, ci, ci, ci, cu, vp, vp, sz, vp]
             f.restype = ci
+        L.q2x_tri_both.argtypes = [vp, i64, vp, i64, vp, vp, vp, vp, vp, i64, ci, ci, ci, cu, vp, vp, vp, sz, vp]
+        L.q2x_tri_both.restype = ci
         L.q2x_bucket_workspace_bytes.argtypes = [i64, i64]
         L.q2x_bucket_workspace_bytes.restype = sz
         L.q2x_bucket.argtypes = [vp, i64, i64, vp, vp, vp, sz, vp]
@@ -105,17 +109,24 @@ def alloc_workspace(kind, n_elems, n_boxes, p, precision=FP32_MIXED, device=None
     return ws[off:off + nbytes]
 
 
+def _out(out, nb, p, device, name="out"):
+    if out is None:
+        return torch.empty((nb, (p + 1) ** 2, 2), dtype=torch.float64, device=device)
+    if tuple(out.shape) != (nb, (p + 1) ** 2, 2):
+        raise Q2XError(f"{name} must have shape {(nb, (p + 1) ** 2, 2)}")
+    return out
+
+
 def run(kind, verts, elems, density, elem_box, box_center, box_radius, p, precision=FP32_MIXED,
         norm=NORM_FMM, accumulate=False, presorted=False, out=None, workspace=None, stream=None):
     """Q2X for one mesh of one element kind; returns out [B, (p+1)^2, 2] float64."""
+    if kind == TRI_BOTH:
+        raise Q2XError("use tri_both() for the two-output kind")
     n_el = int(elems.shape[0]) if elems is not None else 0
     nb = int(box_center.shape[0])
     if elems is not None and elems.dim() == 2 and elems.shape[1] != VERTS_PER_KIND[kind]:
         raise Q2XError(f"elements of kind {KIND_NAMES[kind]} need {VERTS_PER_KIND[kind]} vertices")
-    if out is None:
-        out = torch.empty((nb, (p + 1) ** 2, 2), dtype=torch.float64, device=verts.device)
-    elif tuple(out.shape) != (nb, (p + 1) ** 2, 2):
-        raise Q2XError(f"out must have shape {(nb, (p + 1) ** 2, 2)}")
+    out = _out(out, nb, p, verts.device)
     if workspace is None:
         workspace = alloc_workspace(kind, n_el, nb, p, precision, device=verts.device)
     flags = (ACCUMULATE if accumulate else 0) | (PRESORTED if presorted else 0)
@@ -144,6 +155,34 @@ def segment(*args, **kw):
 
 def tet(*args, **kw):
     return run(TET, *args, **kw)
+
+
+def tri_both(verts, tris, density_single, density_double, elem_box, box_center, box_radius, p,
+             precision=FP32_MIXED, norm=NORM_FMM, accumulate=False, presorted=False, out_single=None,
+             out_double=None, workspace=None, stream=None):
+    """Single and double layer of one triangle mesh in one call: (out_single, out_double)."""
+    n_el = int(tris.shape[0]) if tris is not None else 0
+    nb = int(box_center.shape[0])
+    if tris is not None and tris.dim() == 2 and tris.shape[1] != 3:
+        raise Q2XError("triangles need 3 vertices")
+    out_single = _out(out_single, nb, p, verts.device, "out_single")
+    out_double = _out(out_double, nb, p, verts.device, "out_double")
+    if workspace is None:
+        workspace = alloc_workspace(TRI_BOTH, n_el, nb, p, precision, device=verts.device)
+    flags = (ACCUMULATE if accumulate else 0) | (PRESORTED if presorted else 0)
+    rc = lib().q2x_tri_both(_ptr(verts, torch.float64, "verts"), int(verts.shape[0]),
+                            _ptr(tris, torch.int32, "tris"), n_el,
+                            _ptr(density_single, torch.float64, "density_single"),
+                            _ptr(density_double, torch.float64, "density_double"),
+                            _ptr(elem_box, torch.int32, "elem_box"),
+                            _ptr(box_center, torch.float64, "box_center"),
+                            _ptr(box_radius, torch.float64, "box_radius"),
+                            nb, int(p), int(precision), int(norm), flags,
+                            _ptr(out_single, torch.float64, "out_single"),
+                            _ptr(out_double, torch.float64, "out_double"),
+                            ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream(stream))
+    _check(rc)
+    return out_single, out_double
 
 
 def bucket(elem_box, n_boxes, stream=None, workspace=None):
@@ -182,10 +221,10 @@ def profile_reset():
 
 
 def profile_read():
-    """Per kind (index = kind): (recursion_ms[4], call_ms[4], calls[4]) since the last reset."""
-    a = (ctypes.c_double * 4)()
-    c = (ctypes.c_double * 4)()
-    d = (ctypes.c_int64 * 4)()
+    """Per kind (index = kind): (recursion_ms, call_ms, calls), lists of N_KINDS, since the last reset."""
+    a = (ctypes.c_double * N_KINDS)()
+    c = (ctypes.c_double * N_KINDS)()
+    d = (ctypes.c_int64 * N_KINDS)()
     _check(lib().q2x_profile_read(a, c, d))
     return list(a), list(c), list(d)
 

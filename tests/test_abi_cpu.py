@@ -25,7 +25,7 @@ def declared_functions():
 
 def test_header_declares_entry_points():
     names = declared_functions()
-    for n in ("q2x_tri_single", "q2x_tri_double", "q2x_segment", "q2x_tet", "q2x_workspace_bytes",
+    for n in ("q2x_tri_single", "q2x_tri_double", "q2x_segment", "q2x_tet", "q2x_tri_both", "q2x_workspace_bytes",
               "q2x_status_get", "q2x_bucket"):
         assert n in names
 
@@ -70,6 +70,22 @@ def test_workspace_bytes_and_argument_errors():
     assert rc == -1
     # workspace too small
     rc = L.q2x_tri_single(vp(8), 3, vp(4), 1, vp(8), vp(4), vp(8), vp(8), 1, 8, 0, 0, 0, vp(8), vp(256), 16, None)
+    assert rc == -3
+    # fused single + double: its own workspace size (two sets of partial sums), the
+    # second density and output are required, and the outputs must not overlap
+    assert q2x.workspace_bytes(q2x.TRI_BOTH, 5000, 100, 16) > q2x.workspace_bytes(q2x.TRI_SINGLE, 5000, 100, 16)
+    big = q2x.workspace_bytes(q2x.TRI_BOTH, 10, 4, 4)
+    rc = L.q2x_tri_both(vp(8), 3, vp(4), 1, vp(8), None, vp(4), vp(8), None, 1, 4, 0, 0, 0, vp(8), vp(4096),
+                        vp(256), big, None)
+    assert rc == -1
+    rc = L.q2x_tri_both(vp(8), 3, vp(4), 1, vp(8), vp(8), vp(4), vp(8), None, 1, 4, 0, 0, 0, vp(8), None,
+                        vp(256), big, None)
+    assert rc == -1
+    rc = L.q2x_tri_both(vp(8), 3, vp(4), 1, vp(8), vp(8), vp(4), vp(8), None, 1, 4, 0, 0, 0, vp(4096), vp(4096 + 200),
+                        vp(256), big, None)
+    assert rc == -1  # 25 coefficients x 16 B = 400 B per box: the outputs overlap
+    rc = L.q2x_tri_both(vp(8), 3, vp(4), 1, vp(8), vp(8), vp(4), vp(8), None, 1, 4, 0, 0, 0, vp(8), vp(4096),
+                        vp(256), 16, None)
     assert rc == -3
     assert L.q2x_status_string(-2).startswith(b"Q2X_ERR_P_RANGE")
     assert b"gfx950" in L.q2x_version()
