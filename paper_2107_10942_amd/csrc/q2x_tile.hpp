@@ -27,6 +27,10 @@
 
 namespace q2x {
 
+// Every lambda of the kernel body is inlined: an outlined one would become a
+// real call with its captures on the scratch stack.
+#define Q2X_INLINE __attribute__((always_inline))
+
 template <int N>
 struct IC {
   static constexpr int value = N;
@@ -83,7 +87,7 @@ __device__ __forceinline__ void ladder(CArr<T, P1>& out, const CArr<T, P1>& F, c
     out.r[0] = v;
     out.i[0] = T(0);
   }
-  static_for<1, N + 1>([&](auto MM) {
+  static_for<1, N + 1>([&](auto MM) Q2X_INLINE {
     constexpr int m = decltype(MM)::value;
     const T amr = F.r[m - 1];
     // -xi F^{m-1}:  re -= xr Ar - xi Ai ;  im -= xr Ai + xi Ar
@@ -112,32 +116,27 @@ __device__ __forceinline__ void ladder(CArr<T, P1>& out, const CArr<T, P1>& F, c
   });
 }
 
-// Greedy grouping of the staged outputs into chunks of at most CMAX
-// coefficients.  The unit of grouping is one output of one degree (n + 1
-// coefficients): unit u = NOUT n + s holds degree n, slot s, in the order the
-// recursion produces them, so a chunk may end between the outputs of a degree.
+// Staged coefficients of one element, in the order the recursion produces
+// them: unit u = NOUT n + s is output slot s of degree n (n + 1 coefficients,
+// m = 0..n) and starts at slot off(u).  Chunk j is slots [j CMAX, (j+1) CMAX);
+// a chunk may end inside a unit, whose remaining coefficients open the next.
 template <int P, int CMAX, int NOUT>
 struct ChunkPlan {
-  static constexpr int U = NOUT * (P + 1);  // number of units
-  static constexpr int level(int u) { return u / NOUT; }
-  static constexpr int size(int u) { return u / NOUT + 1; }
+  static constexpr int U = NOUT * (P + 1);      // units
+  static constexpr int K = NOUT * tri(P + 1);   // staged coefficients per element
+  static constexpr int NCHUNK = (K + CMAX - 1) / CMAX;
   static constexpr int off(int u) { return NOUT * tri(u / NOUT) + (u % NOUT) * (u / NOUT + 1); }
-  static constexpr int first_unit(int u) {
-    int s = 0;
-    for (int l = 0; l <= u; ++l)
-      if (off(l + 1) - off(s) > CMAX) s = l;
-    return s;
+  static constexpr int unit_of(int k) {
+    int u = 0;
+    while (off(u + 1) <= k) ++u;
+    return u;
   }
-  static constexpr bool is_end(int u) { return u == U - 1 || first_unit(u + 1) == u + 1; }
-  static constexpr int end_of(int u) {
-    int e = u;
-    while (!is_end(e)) ++e;
-    return e;
-  }
+  static constexpr int first_unit(int j) { return unit_of(j * CMAX); }
+  static constexpr int last_unit(int j) { return unit_of((j * CMAX + CMAX < K ? j * CMAX + CMAX : K) - 1); }
   static constexpr int max_units() {
     int mx = 0;
-    for (int u = 0; u < U; ++u) {
-      const int d = u - first_unit(u) + 1;
+    for (int j = 0; j < NCHUNK; ++j) {
+      const int d = last_unit(j) - first_unit(j) + 1;
       if (d > mx) mx = d;
     }
     return mx;
@@ -202,9 +201,7 @@ struct PrecInfo;
 template <>
 struct PrecInfo<float> {
   static constexpr bool scaled = true;  // FP32 recursion on (y - c)/a_e
-  // 31 coefficients per chunk keep the stage + factor table within 20 KB, so
-  // two wavefronts fit per SIMD (160 KB LDS per CU)
-  static constexpr int cmax = 31;
+  static constexpr int cmax = 32;       // 16.6 KB stage
 };
 template <>
 struct PrecInfo<double> {
@@ -212,7 +209,13 @@ struct PrecInfo<double> {
   static constexpr int cmax = 32;
 };
 
-constexpr double inv_fact(int k) { return k <= 1 ? 1.0 : (k == 2 ? 0.5 : (k == 3 ? 1.0 / 6.0 : 1.0 / 24.0)); }
+// 1/k!, the same sequence of roundings at compile time and at run time
+__host__ __device__ constexpr double inv_factorial(int k) {
+  double f = 1.0;
+  for (int i = 2; i <= k; ++i) f *= (double)i;
+  return 1.0 / f;
+}
+constexpr int kNoExp = -4000;  // exponent of a box segment with no nonzero weight
 
 template <int P, int KIND, typename T>
 __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_tiles) {
@@ -221,17 +224,19 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
   constexpr int NV = KI::nv;
   constexpr int NCH = KI::nch;
   constexpr int NOUT = KI::nout;
-  constexpr int CMAX = (PrecInfo<T>::cmax > P + 1) ? PrecInfo<T>::cmax : P + 1;
-  constexpr int SSTR = kTile + 1;  // padded row stride (elements) of the stage and factor tables
+  constexpr int CMAX = PrecInfo<T>::cmax;  // coefficients per chunk (<= 32: lanes c and c + 32)
+  static_assert(CMAX <= 32, "one lane pair per chunk coefficient");
+  constexpr int SSTR = kTile + 1;  // padded row stride (elements) of the stage
   constexpr int NCT = tri(P + 1);
   constexpr bool SCALED = PrecInfo<T>::scaled;
   using Plan = ChunkPlan<P, CMAX, NOUT>;
-  constexpr int DMAX = Plan::max_units();
 
-  // stage: real part of chunk coefficient c in row c, imaginary part in row CMAX + c
+  // stage: weighted value of chunk coefficient c of every element, real part
+  // in row c, imaginary part in row CMAX + c
   __shared__ T stage[2 * CMAX * SSTR];
-  __shared__ double fac[DMAX * SSTR];         // row u - U0 (unit u of a chunk starting at unit U0)
-  __shared__ int tkey[kTile];                 // box id of every element of the tile
+  // FP32 path: scale exponents of every box segment of the tile (row 0: the
+  // element scales a_e, row 1 + o: the weights s_e of output o)
+  __shared__ int sexp[SCALED ? (NOUT + 1) * kTile : 1];
 
   const int64_t tile = xcd_tile(blockIdx.x, n_tiles);
   const int lane = threadIdx.x;
@@ -335,13 +340,11 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
     vxr2[k] = (T)(X[k][0] * inv_scl);
     vxi2[k] = (T)(X[k][1] * inv_scl);
   }
-  // running FP64 factors s_e a_e^(n - shift) / (n + depth)! of the degree being
-  // produced; s_e = sigma_e J / (4 pi) (Sec. 3.2, Eq. (20)), 0 for skipped elements
-  double fpow[NOUT];
-  static_for<0, NOUT>([&](auto OO) {
+  // s_e = sigma_e J / (4 pi) (Sec. 3.2, Eq. (20)); 0 for skipped elements
+  double sw[NOUT];
+  static_for<0, NOUT>([&](auto OO) Q2X_INLINE {
     constexpr int o = decltype(OO)::value;
-    const double w64 = ok ? sigma[o] * J * kInv4Pi : 0.0;
-    fpow[o] = ((KI::shift(o) == 1) ? w64 * inv_scl : w64) * inv_fact(KI::depth(o));
+    sw[o] = ok ? sigma[o] * J * kInv4Pi : 0.0;
   });
 
   // ---- box start table: box_start[b] = first position whose key >= b, keys
@@ -374,152 +377,255 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
 
   // ---- box boundaries inside the tile (uniform bit mask), open tile edges
   const uint64_t bnd = __ballot(in_range && (lane == 0 || key != key_prev));
-  tkey[lane] = key;  // read after the barrier that opens every chunk reduction
   bool head_open = false, tail_open = false;
   if (q0 > 0) head_open = (a.keys[q0 - 1] == a.keys[q0]);
   if (ne == kTile && q0 + kTile < pos_end) tail_open = (a.keys[q0 + kTile] == a.keys[q0 + kTile - 1]);
   const int p = a.p;
   const int ncoef_out = (p + 1) * (p + 1);
 
-  // ---- reduction of one chunk of units [U0, U1]
-  // lane = (group g, coefficient c): with CMAX <= 32 the two half-waves walk
-  // elements [0,32) and [32,64) of the same coefficient (G = 2), otherwise one
-  // lane walks all 64 (G = 1).  Within a group every box segment is summed in
-  // element order and flushed where it ends; the one segment that may straddle
-  // the halves is summed by both and joined (tail of half 0 + head of half 1).
-  auto flush = [&](int sa, int sb, double accr, double acci, bool wr, int n, int m, double* out, int g_coef) {
-    const int box = tkey[sa];  // (an LDS table: flushes run in lane-divergent code)
-    if (!(wr && box >= 0 && box < a.n_boxes)) return;
-    const bool open = (sa == 0 && head_open) || (sb == kTile && tail_open);
-    if (open) {
-      const int slot = (sa == 0) ? 0 : 1;
-      double* pp = a.partials + ((tile * 2 + slot) * (int64_t)(NOUT * NCT) + g_coef) * 2;
-      pp[0] = accr;
-      pp[1] = acci;
-    } else {
-      finalize_store(out + (int64_t)box * ncoef_out * 2, n, m, accr, acci, a.norm, a.accumulate);
-    }
-  };
-  auto reduce_chunk = [&](auto U0c, auto U1c) {
-    constexpr int U0 = decltype(U0c)::value;
-    constexpr int U1 = decltype(U1c)::value;
-    constexpr int C = Plan::off(U1 + 1) - Plan::off(U0);
-    static_assert(C <= CMAX && U1 - U0 + 1 <= DMAX, "chunk too large");
-    constexpr int G = (CMAX <= 32) ? 2 : 1;
-    constexpr int E = kTile / G;
+  // ---- weights of the staged values.  Output o of degree n of an element is
+  // s_e a_e^(n - shift) G_n / (n + depth)!, G_n the recursion value (on Y =
+  // (y - c)/a_e in FP32, on y - c with a_e = 1 in FP64).
+  //   FP64: the stage holds G_n s_e / (n + depth)!.
+  //   FP32: the stage holds G_n (s_e / 2^Es) (a_e / 2^Eb)^(n - shift), with
+  //   2^Eb >= every a_e and 2^Es >= every |s_e| of the element's box segment in
+  //   the tile, so the weight lies in [-1, 1] and cannot overflow; a weight that
+  //   underflows belongs to an element below 2^-126 of its box's largest.  The
+  //   flush restores 2^((n - shift) Eb + Es) / (n + depth)! in FP64.
+  double wgt[NOUT];
+  double rr = 1.0;     // FP32: a_e / 2^Eb
+  int seg_eb = 0;      // FP32: Eb and Es of this element's box segment (read by
+  int seg_es[NOUT];    // the reduction with readlane at segment starts)
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) seg_es[o] = 0;
+  if constexpr (SCALED) {
+    const int si = __popcll(bnd & ((2ull << lane) - 1)) - 1;  // box segment of this element
+#pragma unroll
+    for (int t = 0; t <= NOUT; ++t) sexp[t * kTile + lane] = kNoExp;
     __syncthreads();
-    const int g = (G == 2) ? (lane >> 5) : 0;
-    const int c = (G == 2) ? (lane & 31) : lane;
-    const bool act = c < C;
-    const int cc = act ? c : 0;
-    // decode chunk coefficient cc -> unit u (degree n, output o), order m
-    int u = U0, r = cc;
-    static_for<U0, U1>([&](auto UU) {
-      constexpr int l = decltype(UU)::value;
-      if (u == l && r >= Plan::size(l)) {
-        r -= Plan::size(l);
+    if (ok) {
+      int ea;
+      (void)frexp(scl, &ea);
+      atomicMax(&sexp[si], ea);
+#pragma unroll
+      for (int o = 0; o < NOUT; ++o) {
+        if (sw[o] != 0.0) {
+          int es;
+          (void)frexp(sw[o], &es);
+          atomicMax(&sexp[(1 + o) * kTile + si], es);
+        }
+      }
+    }
+    __syncthreads();
+    seg_eb = sexp[si];
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) seg_es[o] = sexp[(1 + o) * kTile + si];
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) wgt[o] = 0.0;
+    if (ok) {
+      rr = ldexp(scl, -seg_eb);
+#pragma unroll
+      for (int o = 0; o < NOUT; ++o) wgt[o] = ldexp(sw[o], -seg_es[o]);
+    }
+  } else {
+    static_for<0, NOUT>([&](auto OO) Q2X_INLINE {
+      constexpr int o = decltype(OO)::value;
+      wgt[o] = sw[o] * inv_factorial(KI::depth(o));
+    });
+  }
+
+  // ---- reduction of chunk J (staged slots [J CMAX, J CMAX + CMAX))
+  // Lane c + 32 h holds coefficient c of the chunk, real part (h = 0) or
+  // imaginary part (h = 1), and walks all 64 elements of the tile in order,
+  // summing the staged values in FP64 (elements at even and odd positions in
+  // two partial sums, added where a box segment ends).  Box changes are
+  // therefore the same for every lane; at each one the wave pairs the real and
+  // imaginary sums across the halves (v_permlane32_swap) and lane c stores
+  // coefficient +m, lane c + 32 the coefficient -m.  The walk loads 8 elements
+  // ahead; the box id and scale exponents of a new segment come from the lane
+  // of its first element (readlane), so a segment end touches no LDS.
+  // Elements past ne carry weight 0 and add exact zeros.
+  const uint64_t cuts = bnd & ~1ull;  // bit i: a box segment ends before element i
+  // Reduction of the chunk with first slot K0 (CJ slots); the lane's slot
+  // K0 + c decodes to degree n, output o and order m; shift and invf =
+  // 1/(n + depth)! are output o's.
+  auto reduce_body = [&](int K0, int CJ, int n, int o, int m, int shift, double invf) Q2X_INLINE {
+    constexpr int BATCH = 8;
+    const int h = lane >> 5;
+    const int c = lane & 31;
+    const bool act = c < CJ;
+    const bool live = act && n <= p;             // a requested coefficient
+    const bool wr = live && (h == 0 || m != 0);  // lane h = 1 writes -m for m > 0
+    const int g_coef = o * NCT + tri(n) + m;
+    // Finalisation of a raw tilde sum T = tr + i ti into the +m and -m
+    // coefficients (Sec. 3.4, Eqs. (47),(49); symmetry Eq. (12)):
+    //   FMM    : F^{+m} = base i^{-m} conj(T), F^{-m} = base i^{-m} T, base = (-1)^n
+    //   MOMENT : M^{+m} = base i^{m} T,       M^{-m} = base i^{m} conj(T), base = (-1)^m 4pi
+    // With i^{-m} = fc + i fs (one of fc, fs is 0), cp = base fc, sp = base fs
+    // and eta = +1 (FMM) or -1 (MOMENT):
+    //   +m: (cp tr + sp ti, eta (sp tr - cp ti));  -m: (cp tr - sp ti, eta (sp tr + cp ti)).
+    // F_n^0 is real: its imaginary part (round-off) is written as 0.
+    const int r4 = m & 3;
+    const double fc = (r4 == 0) ? 1.0 : ((r4 == 2) ? -1.0 : 0.0);
+    const double fs = (r4 == 1) ? -1.0 : ((r4 == 3) ? 1.0 : 0.0);
+    const bool fmm = (a.norm == Q2X_NORM_FMM);
+    const double base = fmm ? ((n & 1) ? -1.0 : 1.0) : ((m & 1) ? -k4Pi : k4Pi);
+    const double cp = base * fc, sp = base * fs;
+    const double cq = fmm ? cp : -cp, sq = fmm ? sp : -sp;
+    const bool im0 = (h == 0 && m == 0);
+    const double A1 = cp, A2 = h ? -sp : sp;
+    const double B1 = im0 ? 0.0 : sq, B2 = im0 ? 0.0 : (h ? cq : -cq);
+    const int idx = h ? (n * n + n - m) : (n * n + n + m);
+    double* const obase = ((o == 0) ? a.coeffs : a.coeffs2) + 2 * idx;
+    double* const pbase = a.partials + (tile * 2 * (int64_t)(NOUT * NCT) + g_coef) * 2;
+    const int nsh = (n > shift) ? n - shift : 0;
+    // segment state (uniform): first element, box id, scale exponents
+    int seg = 0;
+    int box = __builtin_amdgcn_readfirstlane(key);
+    int eb = 0, es0 = 0, es1 = 0;
+    if constexpr (SCALED) {
+      eb = __builtin_amdgcn_readfirstlane(seg_eb);
+      es0 = __builtin_amdgcn_readfirstlane(seg_es[0]);
+      es1 = __builtin_amdgcn_readfirstlane(seg_es[NOUT - 1]);
+    }
+    auto flush = [&](int sb, double t) Q2X_INLINE {
+      if (box < 0 || box >= a.n_boxes) return;  // uniform
+      if constexpr (SCALED) t *= ldexp(invf, nsh * eb + ((o == 0) ? es0 : es1));
+      // pair the halves: tr from lane c, ti from lane c + 32, on every lane
+      const uint32_t lo = (uint32_t)__double2loint(t), hi = (uint32_t)__double2hiint(t);
+      const auto slo = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+      const auto shi = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+      const double tr = __hiloint2double((int)shi[0], (int)slo[0]);
+      const double ti = __hiloint2double((int)shi[1], (int)slo[1]);
+      if ((seg == 0 && head_open) || (sb == kTile && tail_open)) {  // uniform: box continues in another tile
+        if (h == 0 && live) {
+          double* pp = pbase + ((seg == 0) ? 0 : (int64_t)(NOUT * NCT) * 2);
+          pp[0] = tr;
+          pp[1] = ti;
+        }
+        return;
+      }
+      if (!wr) return;
+      double x = A1 * tr + A2 * ti, y = B1 * tr + B2 * ti;
+      double* dst = obase + (int64_t)box * ncoef_out * 2;
+      if (a.accumulate) {
+        x += dst[0];
+        y += dst[1];
+      }
+      dst[0] = x;
+      dst[1] = y;
+    };
+    auto next_segment = [&](int i) Q2X_INLINE {
+      seg = i;
+      box = __builtin_amdgcn_readlane(key, i);
+      if constexpr (SCALED) {
+        eb = __builtin_amdgcn_readlane(seg_eb, i);
+        es0 = __builtin_amdgcn_readlane(seg_es[0], i);
+        es1 = __builtin_amdgcn_readlane(seg_es[NOUT - 1], i);
+      }
+    };
+    const T* pv = stage + ((h ? CMAX : 0) + (act ? c : 0)) * SSTR;
+    double a0 = 0.0, a1 = 0.0;  // sums over even / odd positions of the open segment
+    T cur[BATCH];
+    static_for<0, BATCH>([&](auto JB) Q2X_INLINE {
+      constexpr int j = decltype(JB)::value;
+      cur[j] = pv[j];
+    });
+#pragma unroll 1
+    for (int b0 = 0; b0 < kTile; b0 += BATCH) {  // uniform
+      T nxt[BATCH];
+      const int bn = (b0 + BATCH < kTile) ? b0 + BATCH : b0;  // (last batch: a harmless reload)
+      static_for<0, BATCH>([&](auto JB) Q2X_INLINE {
+        constexpr int j = decltype(JB)::value;
+        nxt[j] = pv[bn + j];
+      });
+      const uint32_t uc = (uint32_t)(cuts >> b0) & 0xffu;
+      static_for<0, BATCH>([&](auto JB) Q2X_INLINE {
+        constexpr int j = decltype(JB)::value;
+        if ((uc >> j) & 1u) {  // uniform: a segment ends before element b0 + j
+          flush(b0 + j, a0 + a1);
+          a0 = 0.0;
+          a1 = 0.0;
+          next_segment(b0 + j);
+        }
+        if constexpr (j & 1)
+          a1 += (double)cur[j];
+        else
+          a0 += (double)cur[j];
+      });
+      static_for<0, BATCH>([&](auto JB) Q2X_INLINE {
+        constexpr int j = decltype(JB)::value;
+        cur[j] = nxt[j];
+      });
+    }
+    flush(ne, a0 + a1);  // the tile's last segment
+    __syncthreads();
+  };
+  // chunk J, decoded at compile time (natural chunk ends inside the recursion)
+  auto reduce_chunk = [&](auto JJc) Q2X_INLINE {
+    constexpr int J = decltype(JJc)::value;
+    constexpr int K0 = J * CMAX;
+    constexpr int CJ = (Plan::K - K0 < CMAX) ? Plan::K - K0 : CMAX;
+    constexpr int UF = Plan::first_unit(J), UL = Plan::last_unit(J);
+    __syncthreads();
+    const int c = lane & 31;
+    const int k = K0 + ((c < CJ) ? c : 0);
+    constexpr int OF = (NOUT == 1) ? 0 : ((UF % NOUT) == KI::slot(0) ? 0 : 1);
+    int u = UF, ku = Plan::off(UF), sh = KI::shift(OF);
+    double invf = inv_factorial(UF / NOUT + KI::depth(OF));
+    static_for<UF, UL>([&](auto LL) Q2X_INLINE {
+      constexpr int l = decltype(LL)::value;
+      constexpr int ol = (NOUT == 1) ? 0 : (((l + 1) % NOUT) == KI::slot(0) ? 0 : 1);
+      if (k >= Plan::off(l + 1)) {
         u = l + 1;
+        ku = Plan::off(l + 1);
+        sh = KI::shift(ol);
+        invf = inv_factorial((l + 1) / NOUT + KI::depth(ol));
       }
     });
-    const int n = u / NOUT;
     const int o = (NOUT == 1) ? 0 : ((u % NOUT) == KI::slot(0) ? 0 : 1);
-    const int m = r;
-    const bool wr = act && n <= p;
-    double* out = (o == 0) ? a.coeffs : a.coeffs2;
-    const int g_coef = o * NCT + tri(n) + m;
-    const T* rre = stage + cc * SSTR;
-    const T* rim = stage + (CMAX + cc) * SSTR;
-    const double* frow = fac + (u - U0) * SSTR;
-    const int gs = g * E;
-    const int ge = min(gs + E, ne);
-    const bool cont_in = (g > 0) && (gs < ne) && !((bnd >> gs) & 1ull);
-    double accr = 0.0, acci = 0.0, hr = 0.0, hi = 0.0;
-    int seg = gs, head_end = ge;
-    bool in_head = cont_in;
-    // Walk i = 0..E-1 (element gs + i) in pieces cut at every boundary of
-    // either half, so that each piece is a tight loop with uniform control;
-    // at a cut only the half whose box changes there closes its segment.
-    // Elements past ne carry weight 0 and add exact zeros.
-    const uint64_t mybits = (G == 2) ? (bnd >> gs) : bnd;  // this half's boundaries at i
-    const uint64_t cuts = ((G == 2) ? ((bnd | (bnd >> 32)) & 0xffffffffull) : bnd) & ~1ull;
-    const T* pre = rre + gs;
-    const T* pim = rim + gs;
-    const double* pf = frow + gs;
-    int i0 = 0;
-    while (i0 < E) {  // uniform
-      const uint64_t nxt = (i0 + 1 < 64) ? (cuts >> (i0 + 1)) : 0ull;
-      const int i1 = nxt ? i0 + 1 + __builtin_ctzll(nxt) : E;
-#pragma unroll 4
-      for (int i = i0; i < i1; ++i) {
-        const double f = pf[i];
-        accr = __builtin_fma((double)pre[i], f, accr);
-        acci = __builtin_fma((double)pim[i], f, acci);
-      }
-      if (i1 < E && ((mybits >> i1) & 1ull)) {  // this half's segment ends at gs + i1
-        const int el = gs + i1;
-        if (in_head) {  // the continued segment ends inside this half: keep it for the join
-          hr = accr;
-          hi = acci;
-          head_end = el;
-          in_head = false;
-        } else {
-          flush(seg, el, accr, acci, wr, n, m, out, g_coef);
-        }
-        accr = 0.0;
-        acci = 0.0;
-        seg = el;
-      }
-      i0 = i1;
-    }
-    // last segment of the half: flushed here unless it is joined with the other half
-    const bool cont_out = (G == 2) && (g == 0) && (ge == E) && (E < ne) && !((bnd >> E) & 1ull);
-    if (gs < ne) {
-      if (in_head) {  // continued segment covers the rest of half 1
-        hr = accr;
-        hi = acci;
-        head_end = ge;
-      } else if (!cont_out) {
-        flush(seg, ge, accr, acci, wr, n, m, out, g_coef);
-      }
-    }
-    if constexpr (G == 2) {
-      // join: half 0's open tail + half 1's head (lane c+32 -> lane c)
-      const double jr = __shfl(hr, lane + 32);
-      const double ji = __shfl(hi, lane + 32);
-      const int jend = __shfl(head_end, lane + 32);
-      if (cont_out) flush(seg, jend, accr + jr, acci + ji, wr, n, m, out, g_coef);
-    }
-    __syncthreads();
+    reduce_body(K0, CJ, u / NOUT, o, k - ku, sh, invf);
+  };
+  // unit and order of slot k (run-time decode; units are degree-major)
+  auto decode = [&](int k, int& u, int& ku) Q2X_INLINE {
+    int n, mm;
+    tri_nm(k / NOUT, n, mm);  // NOUT tri(n) <= k < NOUT tri(n + 1)
+    const int r = k - NOUT * tri(n);
+    const int sl = r / (n + 1);
+    u = NOUT * n + sl;
+    ku = NOUT * tri(n) + sl * (n + 1);
   };
 
-  // output o of degree N: stage it and its FP64 factors; reduce at chunk ends
-  // (and after the last output of the requested order when that falls inside
-  // a chunk)
-  auto emit = [&](auto NNc, auto OO, const CArr<T, P1>& V) {
+  // output o of degree N: stage it, weighted, and reduce each chunk as soon
+  // as it is full
+  auto emit = [&](auto NNc, auto OO, const CArr<T, P1>& V) Q2X_INLINE {
     constexpr int N = decltype(NNc)::value;
     constexpr int o = decltype(OO)::value;
     constexpr int u = NOUT * N + KI::slot(o);
-    constexpr int U0 = Plan::first_unit(u);
-    constexpr int row0 = Plan::off(u) - Plan::off(U0);
-    static_for<0, N + 1>([&](auto MM) {
+    constexpr int k0 = Plan::off(u), k1 = Plan::off(u + 1);
+    constexpr int j1 = (k1 - 1) / CMAX;
+    const T w = (T)wgt[o];
+    static_for<0, N + 1>([&](auto MM) Q2X_INLINE {
       constexpr int m = decltype(MM)::value;
-      stage[(row0 + m) * SSTR + lane] = V.r[m];
-      stage[(CMAX + row0 + m) * SSTR + lane] = V.i[m];
+      constexpr int kk = k0 + m;
+      constexpr int row = kk % CMAX;
+      stage[row * SSTR + lane] = V.r[m] * w;
+      stage[(CMAX + row) * SSTR + lane] = V.i[m] * w;
+      if constexpr (row == CMAX - 1) reduce_chunk(IC<kk / CMAX>{});  // chunk kk / CMAX is full
     });
-    fac[(u - U0) * SSTR + lane] = fpow[o];
-    constexpr double inv_next = 1.0 / (double)(N + 1 + KI::depth(o));
-    fpow[o] = fpow[o] * scl * inv_next;
-    if constexpr (Plan::is_end(u)) {
-      reduce_chunk(IC<U0>{}, IC<u>{});
-    } else if (KI::slot(o) == NOUT - 1 && N == p) {
-      reduce_chunk(IC<U0>{}, IC<Plan::end_of(u)>{});
+    if constexpr (SCALED) {
+      if constexpr (N + 1 - KI::shift(o) > 0) wgt[o] *= rr;
+    } else {
+      constexpr double inv_next = 1.0 / (double)(N + 1 + KI::depth(o));
+      wgt[o] *= inv_next;
     }
+    if constexpr (k1 % CMAX != 0 && k1 == Plan::K) reduce_chunk(IC<j1>{});  // last, partly filled chunk
   };
 
   // one degree of every array of the chain: nS (degree N) from S (degree N-1)
-  auto advance = [&](auto NNc, CArr<T, P1>(&nS)[NCH], const CArr<T, P1>(&S)[NCH]) {
+  auto advance = [&](auto NNc, CArr<T, P1>(&nS)[NCH], const CArr<T, P1>(&S)[NCH]) Q2X_INLINE {
     constexpr int N = decltype(NNc)::value;
-    static_for<0, NCH>([&](auto KK) {
+    static_for<0, NCH>([&](auto KK) Q2X_INLINE {
       constexpr int k = decltype(KK)::value;
       constexpr int v = KI::vert(k);
       if constexpr (k == 0)
@@ -540,7 +646,7 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
   constexpr bool HAS_DBL = KI::dbl(NOUT - 1);
   if constexpr (!HAS_DBL) {
     // S holds degree N; emit the chain's last array
-    auto rec = [&](auto self, auto NNc, const CArr<T, P1>(&S)[NCH]) -> void {
+    auto rec = [&](auto self, auto NNc, const CArr<T, P1>(&S)[NCH]) Q2X_INLINE -> void {
       constexpr int N = decltype(NNc)::value;
       emit(IC<N>{}, IC<0>{}, S[NCH - 1]);
       if constexpr (N < P) {
@@ -558,7 +664,7 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
     // S holds degree max(N-1, 0).
     constexpr int OD = NOUT - 1;
     const T hnx = (T)(0.5 * nx), hny = (T)(0.5 * ny), tnz = (T)nz, nx2 = (T)nx, ny2 = (T)ny;
-    auto rec = [&](auto self, auto NNc, const CArr<T, P1>(&S)[NCH]) -> void {
+    auto rec = [&](auto self, auto NNc, const CArr<T, P1>(&S)[NCH]) Q2X_INLINE -> void {
       constexpr int N = decltype(NNc)::value;
       if constexpr (N == 0) {
         CArr<T, P1> Z;
@@ -590,6 +696,22 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
       }
     };
     rec(rec, IC<0>{}, S0);
+  }
+  // a run stopped at p < P: reduce the chunk that holds the last coefficients
+  // of degree p unless it ended exactly there
+  if (p < P) {
+    const int kend = NOUT * tri(p + 1);
+    if (kend % CMAX != 0) {
+      const int J = (kend - 1) / CMAX;
+      const int K0 = J * CMAX;
+      const int CJ = min(CMAX, Plan::K - K0);
+      int u, ku;
+      const int k = K0 + (((lane & 31) < CJ) ? (lane & 31) : 0);
+      decode(k, u, ku);
+      const int o = (NOUT == 1) ? 0 : ((u % NOUT) == KI::slot(0) ? 0 : 1);
+      __syncthreads();
+      reduce_body(K0, CJ, u / NOUT, o, k - ku, KI::shift(o), inv_factorial(u / NOUT + KI::depth(o)));
+    }
   }
 }
 
