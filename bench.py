@@ -29,7 +29,25 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true", help="skip the 1.3M-triangle p=16 roofline workload")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes 5 times (scales the "
+                         "FETCH_SIZE / WRITE_SIZE counters of a profiler run) and exit")
     return ap.parse_args()
+
+
+def stored_traffic(profile, src_hash):
+    """HBM bytes per launch from a committed counter summary, if it measured this source."""
+    path = os.path.join(ROOT, "profiles", profile)
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    if f"`{src_hash}`" not in text:
+        return None  # the kernel changed since the counters were taken
+    for line in text.splitlines():
+        if line.startswith("traffic_bytes_per_launch:"):
+            return int(line.split(":")[1])
+    return None
 
 
 def coef_complex(t):
@@ -45,6 +63,15 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+    if args.copy_calibration:
+        n = args.copy_calibration // 8
+        src = torch.arange(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 8 * n, "launches": 5}))
+        return
 
     from paper_2107_10942_amd import build as libbuild
     from paper_2107_10942_amd import flops, q2x
@@ -123,9 +150,11 @@ def main():
     dom_name = max(mixed["per_kind"], key=lambda k: mixed["per_kind"][k]["recursion_kernel_ms"])
     dom = mixed["per_kind"][dom_name]
     peak = flops.PEAK_VALU_TFLOPS
+    traffic = stored_traffic("q2x_tile_kernel_tri_both_p16_perturbed_sphere_81920_traffic.md", libbuild.source_hash())
     roof = {"bound": "alu", "kernel": f"q2x_tile_kernel<16,{dom_name},float>", "achieved": dom["tflops"],
-            "peak": peak, "unit": "TFLOP/s", "frac": dom["tflops"] / peak, "traffic": None,
-            "launch_ms": dom["recursion_kernel_ms"], "flops_per_launch": dom["algorithmic_flops"]}
+            "peak": peak, "unit": "TFLOP/s", "frac": dom["tflops"] / peak, "traffic": traffic,
+            "launch_ms": dom["recursion_kernel_ms"], "flops_per_launch": dom["algorithmic_flops"],
+            "algorithmic_bytes_per_launch": flops.launch_bytes(q2x.TRI_BOTH, p, N, B)}
 
     line = {
         "metric": "Q2X coefficients/s at p=16, FP32-mixed vs FP64 plain; serving p50/p99 latency",

@@ -37,6 +37,16 @@ def _units():
     return units
 
 
+def source_hash() -> str:
+    """Short hash of the library sources (ties stored profiler figures to the code they measured)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("q2x_tile.hpp", "q2x_internal.hpp", "q2x_api.hip", "q2x_bucket.hip", "q2x_dispatch.hip", "q2x_inst.hip"):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def _headers():
     return [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".hpp")] + \
         [os.path.join(HERE, "..", "include", "q2x.h")]
