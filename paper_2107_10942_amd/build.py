@@ -22,7 +22,7 @@ COMMON = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(HERE, "..", "include")]
 
-SIMPLE = ["q2x_api.hip", "q2x_bucket.hip", "q2x_dispatch.hip"]
+SIMPLE = ["q2x_api.hip", "q2x_bucket.hip", "q2x_dispatch.hip", "q2x_batch.hip"]
 INST = [(k, f) for k in range(5) for f in (0, 1)]
 
 
@@ -41,7 +41,8 @@ def source_hash() -> str:
     """Short hash of the library sources (ties stored profiler figures to the code they measured)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("q2x_tile.hpp", "q2x_internal.hpp", "q2x_api.hip", "q2x_bucket.hip", "q2x_dispatch.hip", "q2x_inst.hip"):
+    for f in ("q2x_tile.hpp", "q2x_internal.hpp", "q2x_api.hip", "q2x_bucket.hip", "q2x_dispatch.hip", "q2x_inst.hip",
+              "q2x_batch.hip"):
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -25,37 +25,11 @@ __global__ __launch_bounds__(256) void q2x_fixup_kernel(FixupArgs f) {
   const int lane = threadIdx.x & 63;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  const int ncoef = (f.p + 1) * (f.p + 1);
-  const int nct_out = tri(f.p + 1);
-  const int NCT = tri(f.P + 1);
-  const int64_t pstride = (int64_t)f.nout * NCT;  // partial sums per (tile, slot)
+  const int64_t ncoef = (int64_t)(f.p + 1) * (f.p + 1);
   for (int64_t b = wave; b < f.n_boxes; b += nwaves) {
     const int64_t s = f.n_pos ? f.box_start[b] : 0, t = f.n_pos ? f.box_start[b + 1] : 0;
-    if (t <= s) {
-      if (!f.accumulate)
-        for (int o = 0; o < f.nout; ++o) {
-          double* row = (o ? f.coeffs2 : f.coeffs) + b * (int64_t)ncoef * 2;
-          for (int i = lane; i < 2 * ncoef; i += 64) row[i] = 0.0;
-        }
-      continue;
-    }
-    const int64_t t0 = s / kTile, t1 = (t - 1) / kTile;
-    if (t0 == t1) continue;  // finished by the tile kernel
-    for (int gg = lane; gg < f.nout * nct_out; gg += 64) {
-      const int o = gg / nct_out;
-      const int g = gg - o * nct_out;
-      double ar = 0.0, ai = 0.0;
-      for (int64_t tt = t0; tt <= t1; ++tt) {
-        const int slot = (tt == t0 && s != t0 * kTile) ? 1 : 0;
-        const double* pp = f.partials + ((tt * 2 + slot) * pstride + o * NCT + g) * 2;
-        ar += pp[0];
-        ai += pp[1];
-      }
-      int n, m;
-      tri_nm(g, n, m);
-      double* row = (o ? f.coeffs2 : f.coeffs) + b * (int64_t)ncoef * 2;
-      finalize_store(row, n, m, ar, ai, f.norm, f.accumulate);
-    }
+    fixup_box(lane, s, t, 0, 0, f.partials, f.coeffs + b * ncoef * 2, f.coeffs2 ? f.coeffs2 + b * ncoef * 2 : nullptr,
+              f.nout, f.p, f.P, f.norm, f.accumulate);
   }
 }
 
@@ -181,7 +155,7 @@ q2x_status run(int kind, const double* verts, int64_t n_verts, const int32_t* el
   }
   if (err != hipSuccess) return Q2X_ERR_HIP;
 
-  TileArgs a;
+  TileArgs a{};
   a.verts = verts;
   a.elems = elems;
   a.density = density;

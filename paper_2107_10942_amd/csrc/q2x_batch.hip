@@ -1,0 +1,466 @@
+// q2x_batch.hip -- many meshes in one replayed launch sequence.
+//
+// A plan groups the jobs by (element kind, precision, order bucket).  One run
+// is: clear the per-job status blocks; build one sort key per element of every
+// job (the job's first global box id + its box id, ids outside the job's box
+// range set aside as invalid); one stable radix sort of all keys, so that
+// every job's elements come out contiguous, grouped by box, in element order
+// inside a box; the start of every global box; one tile launch per group,
+// where every workgroup looks its job up in the group's tile table and works
+// on 64 elements of that job's range only; one fix-up over all boxes.  Tiles
+// never span two jobs and start at the job's first sorted element, so each
+// job's coefficients are bitwise those of the single call on that job.
+//
+// The sequence is captured once into a HIP graph (per workspace) and replayed.
+// Two captures are compared on the first run -- the group launches in one
+// stream order, or as parallel branches of the graph -- unless a job
+// accumulates into its output, and the faster is kept.
+#include <hip/hip_runtime.h>
+
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "q2x_internal.hpp"
+
+namespace q2x {
+hipError_t bucket_elements(const int32_t* elem_box, int64_t n, int64_t nb, int32_t* scratch, Status* status,
+                           hipStream_t s, const int32_t** keys_out, const int32_t** perm_out);
+hipError_t launch_box_bounds(const int32_t* keys, int64_t n, int64_t nb, int32_t* box_start, hipStream_t s);
+size_t bucket_scratch_bytes(int64_t n, int64_t nb);
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+// status blocks [n] <- 0 (a kernel, not a memset: the run is graph-captured)
+__global__ void batch_clear(uint32_t* p, int64_t n_words) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_words; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+// keys[g] = box_base[j] + elem_box_j[e] for element e of job j (g = elem_base[j] + e);
+// ids outside [0, n_boxes_j) -> total_boxes (sorted after every job), counted in job j's status
+__global__ void batch_gather_keys(const BatchJob* __restrict__ jobs, const int64_t* __restrict__ elem_base,
+                                  int n_jobs, int64_t n_total, int64_t total_boxes, int32_t* __restrict__ keys,
+                                  Status* status) {
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    int lo = 0, hi = n_jobs;  // elem_base[lo] <= g < elem_base[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (elem_base[mid] <= g) lo = mid;
+      else hi = mid;
+    }
+    const BatchJob& J = jobs[lo];
+    const int32_t b = J.elem_box[g - elem_base[lo]];
+    if (b >= 0 && b < J.n_boxes) {
+      keys[g] = (int32_t)(J.box_base + b);
+    } else {
+      keys[g] = (int32_t)total_boxes;
+      atomicAdd(&status[lo].n_skipped, 1ull);
+      atomicOr(&status[lo].flags, (uint32_t)Q2X_FLAG_BAD_BOX);
+    }
+  }
+}
+
+// boxes cut by tile edges and empty boxes of every job; one wavefront per global box
+__global__ __launch_bounds__(256) void batch_fixup(const BatchJob* __restrict__ jobs,
+                                                   const int64_t* __restrict__ box_base, int n_jobs,
+                                                   int64_t total_boxes, const int32_t* __restrict__ box_start,
+                                                   const double* __restrict__ parts) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t gb = wave; gb < total_boxes; gb += nwaves) {
+    int lo = 0, hi = n_jobs;  // box_base[lo] <= gb < box_base[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (box_base[mid] <= gb) lo = mid;
+      else hi = mid;
+    }
+    const BatchJob& J = jobs[lo];
+    const int64_t b = gb - J.box_base;
+    const int64_t ncoef = (int64_t)(J.p + 1) * (J.p + 1);
+    fixup_box(lane, box_start[gb], box_start[gb + 1], box_start[J.box_base], J.tile_base, parts + J.part_off,
+              J.coeffs + b * ncoef * 2, J.coeffs2 ? J.coeffs2 + b * ncoef * 2 : nullptr, J.nout, J.p, J.P, J.norm,
+              J.accumulate);
+  }
+}
+
+struct Group {
+  int kind, prec, P, nout;
+  std::vector<int32_t> jobs;
+  std::vector<int64_t> tiles;  // prefix, size jobs + 1
+  int64_t part_off;            // doubles
+};
+
+std::mutex& tune_mu() {
+  static std::mutex m;
+  return m;
+}
+std::map<std::string, int>& tune_cache() {  // plan signature -> capture mode
+  static std::map<std::string, int> c;
+  return c;
+}
+
+}  // namespace
+}  // namespace q2x
+
+using namespace q2x;
+
+struct q2x_plan {
+  int n_jobs = 0;
+  bool any_accumulate = false;
+  std::vector<BatchJob> jobs;
+  std::vector<int64_t> elem_base, box_base;  // size n_jobs + 1
+  std::vector<Group> groups;
+  int64_t n_total = 0, total_boxes = 0;
+  size_t parts_doubles = 0;
+  // device copies of the tables (allocated by the plan)
+  char* dev = nullptr;
+  BatchJob* d_jobs = nullptr;
+  int64_t* d_elem_base = nullptr;
+  int64_t* d_box_base = nullptr;
+  std::vector<int32_t*> d_gjobs;
+  std::vector<int64_t*> d_gtiles;
+  // workspace layout
+  size_t off_status = 0, off_keys = 0, off_sort = 0, off_box_start = 0, off_parts = 0, total = 0;
+  // capture
+  hipStream_t cap[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::vector<hipEvent_t> evs;
+  void* graph_ws = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int mode = -1;
+  std::string signature;
+};
+
+namespace {
+
+bool job_ok(const q2x_job& j) {
+  if (j.kind < Q2X_TRI_SINGLE || j.kind > Q2X_TRI_BOTH) return false;
+  if (j.p < 0 || j.p > Q2X_P_MAX || bucket_order(j.p) < 0) return false;
+  if (j.precision != Q2X_FP64 && j.precision != Q2X_FP32_MIXED) return false;
+  if (j.norm != Q2X_NORM_FMM && j.norm != Q2X_NORM_MOMENT) return false;
+  if (j.flags & ~(unsigned)(Q2X_ACCUMULATE | Q2X_PRESORTED)) return false;
+  if (j.n_verts < 0 || j.n_elems < 0 || j.n_boxes < 0) return false;
+  if (j.n_elems > 0 && (!j.verts || !j.elems || !j.density || !j.elem_box)) return false;
+  if (j.n_boxes > 0 && (!j.coeffs || !j.box_center)) return false;
+  if (j.kind == Q2X_TRI_BOTH && ((j.n_elems > 0 && !j.density2) || (j.n_boxes > 0 && !j.coeffs2))) return false;
+  if (((uintptr_t)j.verts % 8) || ((uintptr_t)j.density % 8) || ((uintptr_t)j.density2 % 8) ||
+      ((uintptr_t)j.box_center % 8) || ((uintptr_t)j.coeffs % 8) || ((uintptr_t)j.coeffs2 % 8) ||
+      ((uintptr_t)j.elems % 4) || ((uintptr_t)j.elem_box % 4))
+    return false;
+  return true;
+}
+
+hipError_t enqueue(q2x_plan* P, char* ws, int mode) {
+  hipStream_t s = P->cap[0];
+  Status* st = (Status*)(ws + P->off_status);
+  int32_t* keys = (int32_t*)(ws + P->off_keys);
+  int32_t* sort_scratch = (int32_t*)(ws + P->off_sort);
+  int32_t* box_start = (int32_t*)(ws + P->off_box_start);
+  double* parts = (double*)(ws + P->off_parts);
+  const int64_t n_words = (int64_t)(P->n_jobs + 1) * (int64_t)(sizeof(Status) / 4);
+  hipLaunchKernelGGL(batch_clear, dim3((unsigned)std::min<int64_t>((n_words + 255) / 256, 1024)), dim3(256), 0, s,
+                     (uint32_t*)st, n_words);
+  const int32_t* skeys = keys;
+  const int32_t* sperm = nullptr;
+  if (P->n_total > 0) {
+    const int64_t blocks = std::min<int64_t>((P->n_total + 255) / 256, 65536);
+    hipLaunchKernelGGL(batch_gather_keys, dim3((unsigned)blocks), dim3(256), 0, s, P->d_jobs, P->d_elem_base,
+                       P->n_jobs, P->n_total, P->total_boxes, keys, st);
+    // the sort's own status block (after the jobs') absorbs its invalid-key count
+    hipError_t e = bucket_elements(keys, P->n_total, P->total_boxes, sort_scratch, st + P->n_jobs, s, &skeys, &sperm);
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = launch_box_bounds(skeys, P->n_total, P->total_boxes, box_start, s);
+  if (e != hipSuccess) return e;
+  hipEvent_t* ev = P->evs.data();
+  const bool par = (mode == 1) && P->groups.size() > 1;
+  if (par) {
+    if (hipEventRecord(ev[0], s) != hipSuccess) return hipErrorUnknown;
+  }
+  for (size_t g = 0; g < P->groups.size(); ++g) {
+    const Group& G = P->groups[g];
+    const int64_t n_tiles = G.tiles.back();
+    if (n_tiles == 0) continue;
+    hipStream_t gs = par ? P->cap[1 + g % 3] : s;
+    if (par && hipStreamWaitEvent(gs, ev[0], 0) != hipSuccess) return hipErrorUnknown;
+    TileArgs a{};
+    a.keys = skeys;
+    a.perm = sperm;
+    a.partials = parts + G.part_off;
+    a.bjobs = P->d_jobs;
+    a.bgroup_jobs = P->d_gjobs[g];
+    a.bgroup_tiles = P->d_gtiles[g];
+    a.bng = (int32_t)G.jobs.size();
+    a.bstatus = st;
+    a.bbox_start = box_start;
+    e = launch_tiles(G.kind, G.prec, G.P, a, n_tiles, gs);
+    if (e != hipSuccess) return e;
+    if (par && hipEventRecord(ev[1 + g], gs) != hipSuccess) return hipErrorUnknown;
+  }
+  if (par)
+    for (size_t g = 0; g < P->groups.size(); ++g)
+      if (P->groups[g].tiles.back() > 0 && hipStreamWaitEvent(s, ev[1 + g], 0) != hipSuccess) return hipErrorUnknown;
+  if (P->total_boxes > 0) {
+    const int64_t blocks = std::min<int64_t>((P->total_boxes + 3) / 4, 65536);
+    hipLaunchKernelGGL(batch_fixup, dim3((unsigned)blocks), dim3(256), 0, s, P->d_jobs, P->d_box_base, P->n_jobs,
+                       P->total_boxes, box_start, parts);
+  }
+  return hipGetLastError();
+}
+
+hipError_t capture(q2x_plan* P, char* ws, int mode, hipGraph_t* g, hipGraphExec_t* x) {
+  if (hipStreamBeginCapture(P->cap[0], hipStreamCaptureModeThreadLocal) != hipSuccess) return hipErrorUnknown;
+  const hipError_t e = enqueue(P, ws, mode);
+  hipGraph_t graph = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(P->cap[0], &graph);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return e != hipSuccess ? e : e2;
+  }
+  if (hipGraphInstantiate(x, graph, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return hipErrorUnknown;
+  }
+  *g = graph;
+  return hipSuccess;
+}
+
+void drop_graph(q2x_plan* P) {
+  if (P->exec) (void)hipGraphExecDestroy(P->exec);
+  if (P->graph) (void)hipGraphDestroy(P->graph);
+  P->exec = nullptr;
+  P->graph = nullptr;
+  P->graph_ws = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+q2x_status q2x_batch_plan(const q2x_job* jobs, int n_jobs, q2x_plan** out) {
+  if (!out) return Q2X_ERR_ARG;
+  *out = nullptr;
+  if (!jobs || n_jobs <= 0) return Q2X_ERR_ARG;
+  for (int j = 0; j < n_jobs; ++j)
+    if (!job_ok(jobs[j])) return (jobs[j].p < 0 || jobs[j].p > Q2X_P_MAX) ? Q2X_ERR_P_RANGE : Q2X_ERR_ARG;
+  q2x_plan* P = new q2x_plan();
+  P->n_jobs = n_jobs;
+  P->jobs.resize(n_jobs);
+  P->elem_base.assign(n_jobs + 1, 0);
+  P->box_base.assign(n_jobs + 1, 0);
+  std::map<std::tuple<int, int, int>, int> gidx;
+  for (int j = 0; j < n_jobs; ++j) {
+    const q2x_job& q = jobs[j];
+    P->elem_base[j + 1] = P->elem_base[j] + q.n_elems;
+    P->box_base[j + 1] = P->box_base[j] + q.n_boxes;
+    if (q.flags & Q2X_ACCUMULATE) P->any_accumulate = true;
+    const int Pb = bucket_order(q.p);
+    const auto key = std::make_tuple(q.kind, q.precision, Pb);
+    if (!gidx.count(key)) {
+      gidx[key] = (int)P->groups.size();
+      Group G;
+      G.kind = q.kind;
+      G.prec = q.precision;
+      G.P = Pb;
+      G.nout = (q.kind == Q2X_TRI_BOTH) ? 2 : 1;
+      G.tiles.push_back(0);
+      G.part_off = 0;
+      P->groups.push_back(G);
+    }
+    Group& G = P->groups[gidx[key]];
+    BatchJob& J = P->jobs[j];
+    J = BatchJob{};
+    J.verts = q.verts;
+    J.elems = q.elems;
+    J.density = q.density;
+    J.density2 = (q.kind == Q2X_TRI_BOTH) ? q.density2 : nullptr;
+    J.elem_box = q.elem_box;
+    J.box_center = q.box_center;
+    J.coeffs = q.coeffs;
+    J.coeffs2 = (q.kind == Q2X_TRI_BOTH) ? q.coeffs2 : nullptr;
+    J.n_verts = q.n_verts;
+    J.n_elems = q.n_elems;
+    J.n_boxes = q.n_boxes;
+    J.elem_base = P->elem_base[j];
+    J.box_base = P->box_base[j];
+    J.tile_base = G.tiles.back();
+    J.kind = q.kind;
+    J.prec = q.precision;
+    J.P = Pb;
+    J.p = q.p;
+    J.norm = q.norm;
+    J.accumulate = (q.flags & Q2X_ACCUMULATE) ? 1 : 0;
+    J.nout = G.nout;
+    J.group = gidx[key];
+    G.jobs.push_back(j);
+    G.tiles.push_back(G.tiles.back() + (q.n_elems + kTile - 1) / kTile);
+  }
+  P->n_total = P->elem_base[n_jobs];
+  P->total_boxes = P->box_base[n_jobs];
+  if (P->n_total >= ((int64_t)1 << 31) - 64 || P->total_boxes >= ((int64_t)1 << 31) - 1) {
+    delete P;
+    return Q2X_ERR_ARG;
+  }
+  size_t parts = 0;
+  for (Group& G : P->groups) {
+    G.part_off = (int64_t)parts;
+    parts += (size_t)G.tiles.back() * 2 * (size_t)G.nout * (size_t)tri(G.P + 1) * 2;
+    parts = (parts + 31) & ~(size_t)31;  // 256-byte aligned group regions
+  }
+  for (BatchJob& J : P->jobs) J.part_off = P->groups[J.group].part_off;
+  P->parts_doubles = parts;
+  // workspace layout
+  size_t off = 0;
+  P->off_status = off;
+  off += align_up((size_t)(n_jobs + 1) * sizeof(Status));
+  P->off_keys = off;
+  off += align_up((size_t)P->n_total * sizeof(int32_t) + 4);
+  P->off_sort = off;
+  off += align_up(bucket_scratch_bytes(P->n_total, P->total_boxes));
+  P->off_box_start = off;
+  off += align_up((size_t)(P->total_boxes + 1) * sizeof(int32_t));
+  P->off_parts = off;
+  off += align_up(parts * sizeof(double) + 8);
+  P->total = off;
+  // device tables, one allocation
+  size_t dbytes = align_up(sizeof(BatchJob) * n_jobs) + 2 * align_up(sizeof(int64_t) * (n_jobs + 1));
+  for (const Group& G : P->groups)
+    dbytes += align_up(sizeof(int32_t) * G.jobs.size()) + align_up(sizeof(int64_t) * G.tiles.size());
+  if (hipMalloc((void**)&P->dev, dbytes) != hipSuccess) {
+    delete P;
+    return Q2X_ERR_HIP;
+  }
+  std::vector<char> host(dbytes, 0);
+  size_t o = 0;
+  auto place = [&](const void* src, size_t n) {
+    memcpy(host.data() + o, src, n);
+    char* d = P->dev + o;
+    o += align_up(n);
+    return d;
+  };
+  P->d_jobs = (BatchJob*)place(P->jobs.data(), sizeof(BatchJob) * n_jobs);
+  P->d_elem_base = (int64_t*)place(P->elem_base.data(), sizeof(int64_t) * (n_jobs + 1));
+  P->d_box_base = (int64_t*)place(P->box_base.data(), sizeof(int64_t) * (n_jobs + 1));
+  for (const Group& G : P->groups) {
+    P->d_gjobs.push_back((int32_t*)place(G.jobs.data(), sizeof(int32_t) * G.jobs.size()));
+    P->d_gtiles.push_back((int64_t*)place(G.tiles.data(), sizeof(int64_t) * G.tiles.size()));
+  }
+  bool ok = hipMemcpy(P->dev, host.data(), dbytes, hipMemcpyHostToDevice) == hipSuccess;
+  for (int i = 0; i < 4 && ok; ++i) ok = hipStreamCreateWithFlags(&P->cap[i], hipStreamNonBlocking) == hipSuccess;
+  P->evs.resize(P->groups.size() + 1, nullptr);
+  for (auto& e : P->evs)
+    if (ok) ok = hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    q2x_batch_destroy(P);
+    return Q2X_ERR_HIP;
+  }
+  // signature of the launch shapes (autotune cache key)
+  std::string sig;
+  for (const Group& G : P->groups)
+    sig += std::to_string(G.kind) + "," + std::to_string(G.prec) + "," + std::to_string(G.P) + "," +
+           std::to_string(G.tiles.back()) + ";";
+  sig += std::to_string(P->n_total) + "/" + std::to_string(P->total_boxes);
+  P->signature = sig;
+  *out = P;
+  return Q2X_OK;
+}
+
+size_t q2x_batch_workspace_bytes(const q2x_plan* plan) { return plan ? plan->total : 0; }
+
+int q2x_batch_groups(const q2x_plan* plan) { return plan ? (int)plan->groups.size() : 0; }
+
+int q2x_batch_mode(const q2x_plan* plan) { return plan ? plan->mode : -1; }
+
+q2x_status q2x_batch_run(q2x_plan* plan, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!plan) return Q2X_ERR_ARG;
+  if (!workspace || ((uintptr_t)workspace % kAlign) != 0 || workspace_bytes < plan->total) return Q2X_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  if (plan->exec && plan->graph_ws == workspace)
+    return hipGraphLaunch(plan->exec, s) == hipSuccess ? Q2X_OK : Q2X_ERR_HIP;
+  drop_graph(plan);
+  int mode = 0;
+  bool tuned = false;
+  {
+    std::lock_guard<std::mutex> g(tune_mu());
+    auto it = tune_cache().find(plan->signature);
+    if (it != tune_cache().end()) {
+      mode = it->second;
+      tuned = true;
+    }
+  }
+  char* ws = (char*)workspace;
+  if (!tuned && !plan->any_accumulate && plan->groups.size() > 1) {
+    // time both captures (each replay computes the full, idempotent result)
+    float best = 0.f;
+    for (int m = 0; m < 2; ++m) {
+      hipGraph_t gr = nullptr;
+      hipGraphExec_t ex = nullptr;
+      if (capture(plan, ws, m, &gr, &ex) != hipSuccess) return Q2X_ERR_HIP;
+      hipEvent_t e0, e1;
+      (void)hipEventCreate(&e0);
+      (void)hipEventCreate(&e1);
+      (void)hipGraphLaunch(ex, s);
+      (void)hipEventRecord(e0, s);
+      for (int r = 0; r < 2; ++r) (void)hipGraphLaunch(ex, s);
+      (void)hipEventRecord(e1, s);
+      float ms = 0.f;
+      const bool okt = hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      if (!okt) {
+        (void)hipGraphExecDestroy(ex);
+        (void)hipGraphDestroy(gr);
+        return Q2X_ERR_HIP;
+      }
+      if (m == 0 || ms < best) {
+        drop_graph(plan);
+        best = ms;
+        plan->graph = gr;
+        plan->exec = ex;
+        plan->mode = m;
+      } else {
+        (void)hipGraphExecDestroy(ex);
+        (void)hipGraphDestroy(gr);
+      }
+    }
+    std::lock_guard<std::mutex> g(tune_mu());
+    tune_cache()[plan->signature] = plan->mode;
+    plan->graph_ws = workspace;
+    return Q2X_OK;  // the last replay left the result in place
+  }
+  if (capture(plan, ws, mode, &plan->graph, &plan->exec) != hipSuccess) return Q2X_ERR_HIP;
+  plan->mode = mode;
+  plan->graph_ws = workspace;
+  return hipGraphLaunch(plan->exec, s) == hipSuccess ? Q2X_OK : Q2X_ERR_HIP;
+}
+
+q2x_status q2x_batch_job_status(const q2x_plan* plan, const void* workspace, int job, void* stream,
+                                uint32_t* device_flags, int64_t* n_degenerate, int64_t* n_skipped) {
+  if (!plan || !workspace || job < 0 || job >= plan->n_jobs) return Q2X_ERR_ARG;
+  return q2x_status_get((const char*)workspace + plan->off_status + (size_t)job * sizeof(Status), stream,
+                        device_flags, n_degenerate, n_skipped);
+}
+
+void q2x_batch_destroy(q2x_plan* plan) {
+  if (!plan) return;
+  drop_graph(plan);
+  for (auto& e : plan->evs)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& c : plan->cap)
+    if (c) (void)hipStreamDestroy(c);
+  if (plan->dev) (void)hipFree(plan->dev);
+  delete plan;
+}
+
+}  // extern "C"

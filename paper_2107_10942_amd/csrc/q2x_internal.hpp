@@ -26,7 +26,12 @@ static_assert(sizeof(Status) == 64, "status block is 64 bytes");
 // Number of m >= 0 ("tilde") coefficients of degrees 0..n-1.
 __host__ __device__ constexpr int tri(int n) { return n * (n + 1) / 2; }
 
-// Arguments of the recursion + reduction kernel.
+struct BatchJob;
+
+// Arguments of the recursion + reduction kernel.  A single call fills the
+// per-mesh fields; a batch launch (one group of jobs of the same kind,
+// precision and order bucket) sets `bjobs`, and every workgroup then takes its
+// job's fields from the job table.
 struct TileArgs {
   const double* verts;
   const int32_t* elems;
@@ -46,6 +51,31 @@ struct TileArgs {
   int p;                     // requested order (<= template P)
   int norm;
   int accumulate;
+  // batch launch (nullptr otherwise)
+  const BatchJob* bjobs;       // job table
+  const int32_t* bgroup_jobs;  // [bng] jobs of this launch
+  const int64_t* bgroup_tiles; // [bng + 1] tile prefix of those jobs
+  int32_t bng;
+  Status* bstatus;             // [n_jobs] status blocks
+  const int32_t* bbox_start;   // [total boxes + 1] start of every global box in the sorted order
+};
+
+// One job of a batch as the kernels see it (device table built by the plan).
+struct BatchJob {
+  const double* verts;
+  const int32_t* elems;
+  const double* density;
+  const double* density2;
+  const int32_t* elem_box;
+  const double* box_center;
+  double* coeffs;
+  double* coeffs2;
+  int64_t n_verts, n_elems, n_boxes;
+  int64_t elem_base;   // first element in the concatenation of all jobs
+  int64_t box_base;    // first global box id
+  int64_t tile_base;   // first tile of the job within its group's launch
+  int64_t part_off;    // offset (doubles) of the job's group partials in the workspace
+  int32_t kind, prec, P, p, norm, accumulate, nout, group;
 };
 
 // Arguments of the fix-up kernel (boxes cut by tile edges, empty boxes).
@@ -126,6 +156,42 @@ __device__ __forceinline__ void tri_nm(int g, int& n, int& m) {
   while (tri(nn) > g) --nn;
   n = nn;
   m = g - tri(nn);
+}
+
+// Sum the per-tile partials of box b (positions [s, t) of a sorted range
+// whose tiles start at position base; tiles numbered from tile0), finalise
+// and store.  Empty boxes get zeros unless accumulating.  One wavefront.
+__device__ __forceinline__ void fixup_box(int lane, int64_t s, int64_t t, int64_t base, int64_t tile0,
+                                          const double* partials, double* c0, double* c1, int nout, int p, int P,
+                                          int norm, int accumulate) {
+  const int ncoef = (p + 1) * (p + 1);
+  if (t <= s) {
+    if (!accumulate)
+      for (int o = 0; o < nout; ++o) {
+        double* row = o ? c1 : c0;
+        for (int i = lane; i < 2 * ncoef; i += 64) row[i] = 0.0;
+      }
+    return;
+  }
+  const int64_t t0 = (s - base) / kTile, t1 = (t - 1 - base) / kTile;
+  if (t0 == t1) return;  // finished by the tile kernel
+  const int nct_out = tri(p + 1);
+  const int NCT = tri(P + 1);
+  const int64_t pstride = (int64_t)nout * NCT;  // partial sums per (tile, slot)
+  for (int gg = lane; gg < nout * nct_out; gg += 64) {
+    const int o = gg / nct_out;
+    const int g = gg - o * nct_out;
+    double ar = 0.0, ai = 0.0;
+    for (int64_t tt = t0; tt <= t1; ++tt) {
+      const int slot = (tt == t0 && s != base + t0 * kTile) ? 1 : 0;
+      const double* pp = partials + (((tile0 + tt) * 2 + slot) * pstride + o * NCT + g) * 2;
+      ar += pp[0];
+      ai += pp[1];
+    }
+    int n, m;
+    tri_nm(g, n, m);
+    finalize_store(o ? c1 : c0, n, m, ar, ai, norm, accumulate);
+  }
 }
 
 }  // namespace q2x

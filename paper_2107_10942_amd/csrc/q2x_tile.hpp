@@ -218,7 +218,7 @@ __host__ __device__ constexpr double inv_factorial(int k) {
 constexpr int kNoExp = -4000;  // exponent of a box segment with no nonzero weight
 
 template <int P, int KIND, typename T>
-__global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_tiles) {
+__global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t n_tiles) {
   using KI = KindInfo<KIND>;
   constexpr int P1 = P + 1;
   constexpr int NV = KI::nv;
@@ -240,17 +240,50 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
 
   const int64_t tile = xcd_tile(blockIdx.x, n_tiles);
   const int lane = threadIdx.x;
-  const int64_t q0 = tile * kTile;
-  const int64_t pos_end = a.n_pos;
-  if (q0 >= pos_end) return;  // uniform (never taken with the host's grid)
+  TileArgs a = args;
+  int64_t q0 = tile * kTile;   // first sorted position of the tile
+  int64_t pos_end = a.n_pos;   // end of the sorted range the tile belongs to
+  int64_t key_off = 0;         // sorted keys are key_off + box id
+  int64_t elem_off = 0;        // the permutation holds elem_off + element index
+  const bool batch = (a.bjobs != nullptr);
+  if (batch) {
+    // this tile's job: tiles [bgroup_tiles[j], bgroup_tiles[j + 1]) belong to job bgroup_jobs[j]
+    int lo = 0, hi = a.bng;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (a.bgroup_tiles[mid] <= tile) lo = mid;
+      else hi = mid;
+    }
+    const int jid = a.bgroup_jobs[lo];
+    const BatchJob& J = a.bjobs[jid];
+    a.verts = J.verts;
+    a.elems = J.elems;
+    a.density = J.density;
+    a.density2 = J.density2;
+    a.box_center = J.box_center;
+    a.coeffs = J.coeffs;
+    a.coeffs2 = J.coeffs2;
+    a.status = a.bstatus + jid;
+    a.n_verts = J.n_verts;
+    a.n_boxes = J.n_boxes;
+    a.p = J.p;
+    a.norm = J.norm;
+    a.accumulate = J.accumulate;
+    key_off = J.box_base;
+    const int64_t s0 = a.bbox_start[J.box_base];
+    pos_end = a.bbox_start[J.box_base + J.n_boxes];
+    q0 = s0 + (tile - a.bgroup_tiles[lo]) * kTile;
+    elem_off = J.elem_base;  // positions in the concatenation of all jobs
+  }
+  if (q0 >= pos_end) return;  // uniform (past the job's valid elements)
   const int ne = (int)min<int64_t>(kTile, pos_end - q0);
   const int64_t q = q0 + lane;
   const bool in_range = lane < ne;
 
   // ---- element, box and FP64 geometry (Sec. 3.1, Eqs. (8)-(9); Sec. 3.3, Eq. (21))
-  const int key = in_range ? a.keys[q] : INT32_MIN;
+  const int key = in_range ? (int)(a.keys[q] - key_off) : INT32_MIN;
   const bool box_ok = in_range && key >= 0 && key < a.n_boxes;  // (bad ids were counted by the bucketing)
-  const int64_t e = in_range ? (a.perm ? (int64_t)a.perm[q] : q) : 0;
+  const int64_t e = in_range ? (a.perm ? (int64_t)a.perm[q] - elem_off : q) : 0;
   uint32_t flag = 0;
   bool ok = box_ok;
   double xv[NV][3];
@@ -349,8 +382,8 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs a, int64_t n_t
 
   // ---- box start table: box_start[b] = first position whose key >= b, keys
   // outside [0, B) counting as -1 / B (the fix-up kernel reads it)
-  const int key_prev = (in_range && q > 0) ? a.keys[q - 1] : INT32_MIN;
-  if (in_range) {
+  const int key_prev = (in_range && q > 0) ? (int)(a.keys[q - 1] - key_off) : INT32_MIN;
+  if (in_range && !batch) {
     const int64_t nb = a.n_boxes;
     const int64_t kc = key < 0 ? -1 : (key >= nb ? nb : key);
     const int64_t kp = (q == 0 || key_prev < 0) ? -1 : (key_prev >= nb ? nb : key_prev);

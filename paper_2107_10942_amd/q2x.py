@@ -26,11 +26,21 @@ P_MAX = 32
 FLAG_BAD_BOX, FLAG_NONFINITE, FLAG_RESERVED, FLAG_BAD_VERTEX, FLAG_NOT_SORTED = 1, 2, 4, 8, 16
 EXPORTS = ("q2x_workspace_bytes", "q2x_bucket_workspace_bytes", "q2x_bucket", "q2x_tri_single", "q2x_tri_double", "q2x_segment", "q2x_tet",
            "q2x_tri_both", "q2x_status_get", "q2x_status_string", "q2x_profile_enable", "q2x_profile_reset",
-           "q2x_profile_read", "q2x_version")
+           "q2x_profile_read", "q2x_version", "q2x_batch_plan", "q2x_batch_workspace_bytes", "q2x_batch_run",
+           "q2x_batch_job_status", "q2x_batch_groups", "q2x_batch_mode", "q2x_batch_destroy")
 
 
 class Q2XError(RuntimeError):
     pass
+
+
+class Job(ctypes.Structure):
+    """Mirror of `q2x_job` (include/q2x.h)."""
+    _fields_ = [("kind", ctypes.c_int), ("p", ctypes.c_int), ("precision", ctypes.c_int), ("norm", ctypes.c_int),
+                ("flags", ctypes.c_uint), ("verts", ctypes.c_void_p), ("n_verts", ctypes.c_int64),
+                ("elems", ctypes.c_void_p), ("n_elems", ctypes.c_int64), ("density", ctypes.c_void_p),
+                ("density2", ctypes.c_void_p), ("elem_box", ctypes.c_void_p), ("box_center", ctypes.c_void_p),
+                ("n_boxes", ctypes.c_int64), ("coeffs", ctypes.c_void_p), ("coeffs2", ctypes.c_void_p)]
 
 
 _lib = None
@@ -69,6 +79,21 @@ def lib():
                                        ctypes.POINTER(ctypes.c_int64)]
         L.q2x_profile_read.restype = ci
         L.q2x_version.restype = ctypes.c_char_p
+        L.q2x_batch_plan.argtypes = [ctypes.POINTER(Job), ci, ctypes.POINTER(vp)]
+        L.q2x_batch_plan.restype = ci
+        L.q2x_batch_workspace_bytes.argtypes = [vp]
+        L.q2x_batch_workspace_bytes.restype = sz
+        L.q2x_batch_run.argtypes = [vp, vp, sz, vp]
+        L.q2x_batch_run.restype = ci
+        L.q2x_batch_job_status.argtypes = [vp, vp, ci, vp, ctypes.POINTER(ctypes.c_uint32),
+                                           ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+        L.q2x_batch_job_status.restype = ci
+        L.q2x_batch_groups.argtypes = [vp]
+        L.q2x_batch_groups.restype = ci
+        L.q2x_batch_mode.argtypes = [vp]
+        L.q2x_batch_mode.restype = ci
+        L.q2x_batch_destroy.argtypes = [vp]
+        L.q2x_batch_destroy.restype = None
         _lib = L
     return _lib
 
@@ -183,6 +208,91 @@ def tri_both(verts, tris, density_single, density_double, elem_box, box_center, 
                             ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream(stream))
     _check(rc)
     return out_single, out_double
+
+
+class BatchPlan:
+    """A batch of jobs (q2x_batch_plan / q2x_batch_run).  `jobs` is a list of
+    dicts with the single-call arguments: kind, verts, elems, density,
+    elem_box, box_center, p, and optionally precision, norm, accumulate,
+    out (and density2 / out2 for TRI_BOTH).  Outputs are allocated when not
+    given; the tensors are kept alive by the plan."""
+
+    def __init__(self, jobs):
+        self._keep = []
+        arr = (Job * len(jobs))()
+        self.outs = []
+        for i, j in enumerate(jobs):
+            kind = int(j["kind"])
+            p = int(j["p"])
+            nb = int(j["box_center"].shape[0])
+            dev = j["verts"].device
+            out = _out(j.get("out"), nb, p, dev)
+            out2 = _out(j.get("out2"), nb, p, dev, "out2") if kind == TRI_BOTH else None
+            self.outs.append((out, out2) if kind == TRI_BOTH else out)
+            flags = (ACCUMULATE if j.get("accumulate") else 0) | (PRESORTED if j.get("presorted") else 0)
+            elems = j["elems"]
+            if elems.dim() == 2 and elems.shape[1] != VERTS_PER_KIND[kind]:
+                raise Q2XError(f"job {i}: elements of kind {KIND_NAMES[kind]} need {VERTS_PER_KIND[kind]} vertices")
+            arr[i] = Job(kind, p, int(j.get("precision", FP32_MIXED)), int(j.get("norm", NORM_FMM)), flags,
+                         _ptr(j["verts"], torch.float64, "verts"), int(j["verts"].shape[0]),
+                         _ptr(elems, torch.int32, "elems"), int(elems.shape[0]),
+                         _ptr(j["density"], torch.float64, "density"),
+                         _ptr(j.get("density2"), torch.float64, "density2"),
+                         _ptr(j["elem_box"], torch.int32, "elem_box"),
+                         _ptr(j["box_center"], torch.float64, "box_center"), nb,
+                         _ptr(out, torch.float64, "out"), _ptr(out2, torch.float64, "out2"))
+            self._keep.append((j, out, out2))
+        self._arr = arr
+        self.n_jobs = len(jobs)
+        h = ctypes.c_void_p()
+        _check(lib().q2x_batch_plan(arr, len(jobs), ctypes.byref(h)))
+        self._h = h
+        self.workspace = None
+
+    def workspace_bytes(self):
+        return int(lib().q2x_batch_workspace_bytes(self._h))
+
+    def alloc_workspace(self, device=None):
+        nbytes = self.workspace_bytes()
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device or "cuda")
+        off = (-ws.data_ptr()) % 256
+        self.workspace = ws[off:off + nbytes]
+        return self.workspace
+
+    def run(self, workspace=None, stream=None):
+        if workspace is None:
+            workspace = self.workspace if self.workspace is not None else self.alloc_workspace()
+        _check(lib().q2x_batch_run(self._h, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                   _stream(stream)))
+        return self.outs
+
+    def status(self, j, workspace=None, stream=None):
+        workspace = self.workspace if workspace is None else workspace
+        f = ctypes.c_uint32(0)
+        d = ctypes.c_int64(0)
+        s = ctypes.c_int64(0)
+        _check(lib().q2x_batch_job_status(self._h, ctypes.c_void_p(workspace.data_ptr()), int(j), _stream(stream),
+                                          ctypes.byref(f), ctypes.byref(d), ctypes.byref(s)))
+        return int(f.value), int(d.value), int(s.value)
+
+    @property
+    def groups(self):
+        return int(lib().q2x_batch_groups(self._h))
+
+    @property
+    def mode(self):
+        return int(lib().q2x_batch_mode(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().q2x_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def bucket(elem_box, n_boxes, stream=None, workspace=None):

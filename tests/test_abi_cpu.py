@@ -87,5 +87,21 @@ def test_workspace_bytes_and_argument_errors():
     rc = L.q2x_tri_both(vp(8), 3, vp(4), 1, vp(8), vp(8), vp(4), vp(8), None, 1, 4, 0, 0, 0, vp(8), vp(4096),
                         vp(256), 16, None)
     assert rc == -3
+    # batch plans: argument errors return before any device work
+    h = ctypes.c_void_p()
+    assert L.q2x_batch_plan(None, 1, ctypes.byref(h)) == -1
+    J = (q2x.Job * 2)()
+    assert L.q2x_batch_plan(J, 0, ctypes.byref(h)) == -1
+    J[0] = q2x.Job(7, 4, 0, 0, 0, None, 0, None, 0, None, None, None, None, 0, None, None)  # bad kind
+    J[1] = q2x.Job(0, 4, 0, 0, 0, None, 0, None, 0, None, None, None, None, 0, None, None)
+    assert L.q2x_batch_plan(J, 2, ctypes.byref(h)) == -1 and not h.value
+    J[0] = q2x.Job(0, 40, 0, 0, 0, None, 0, None, 0, None, None, None, None, 0, None, None)  # p out of range
+    assert L.q2x_batch_plan(J, 2, ctypes.byref(h)) == -2
+    J[0] = q2x.Job(1, 8, 0, 0, 0, None, 3, None, 5, None, None, None, None, 0, None, None)  # elements, no arrays
+    assert L.q2x_batch_plan(J, 2, ctypes.byref(h)) == -1
+    J[0] = q2x.Job(4, 8, 0, 0, 0, vp(8), 3, vp(4), 5, vp(8), None, vp(4), vp(8), 2, vp(8), vp(64))  # both: no density2
+    assert L.q2x_batch_plan(J, 2, ctypes.byref(h)) == -1
+    assert L.q2x_batch_workspace_bytes(None) == 0 and L.q2x_batch_mode(None) == -1
+    L.q2x_batch_destroy(None)
     assert L.q2x_status_string(-2).startswith(b"Q2X_ERR_P_RANGE")
     assert b"gfx950" in L.q2x_version()
