@@ -28,6 +28,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true", help="skip the 1.3M-triangle p=16 roofline workload")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 256-mesh batch workload")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving (Poisson arrivals) workload")
+    ap.add_argument("--no-configs", action="store_true", help="skip the icosphere / tetrahedra / filament workloads")
+    ap.add_argument("--serving-requests", type=int, default=500)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes 5 times (scales the "
@@ -48,6 +52,160 @@ def stored_traffic(profile, src_hash):
         if line.startswith("traffic_bytes_per_launch:"):
             return int(line.split(":")[1])
     return None
+
+
+def batch_workload(dev, reps=5):
+    """256 uneven meshes (perturbed spheres / ellipsoids, N log-uniform in [1k, 200k], p in {4..20},
+    single/double): one replayed batch graph vs the same jobs as sequential single calls."""
+    import numpy as np
+    import torch
+
+    from paper_2107_10942_amd import q2x
+    from q2x_inputs import configs
+    jobs = configs.batch_meshes()
+    tens = [q2x.job_tensors(j, dev) for j in jobs]
+    coefs = sum(j.n_elems * (j.p + 1) ** 2 for j in jobs)
+    out = {"workload": f"{len(jobs)} meshes, {sum(j.n_elems for j in jobs)} triangles, "
+                       f"{sum(j.n_boxes for j in jobs)} boxes, p in {{4,8,12,16,20}}, single/double",
+           "element_coefficients": coefs}
+
+    def timed(fn, n):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(n):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    results = {}
+    for prec, name in ((q2x.FP32_MIXED, "fp32_mixed"), (q2x.FP64, "fp64")):
+        specs = [dict(kind=j.kind, verts=t[0], elems=t[1], density=t[2], elem_box=t[3], box_center=t[4], p=j.p,
+                      precision=prec) for j, t in zip(jobs, tens)]
+        plan = q2x.BatchPlan(specs)
+        plan.alloc_workspace(dev)
+        plan.run()
+        torch.cuda.synchronize()
+        ms_batch = timed(plan.run, reps)
+        # the same jobs as single calls, one after the other (each with its own bucketing)
+        wsz = max(q2x.workspace_bytes(j.kind, j.n_elems, j.n_boxes, j.p, prec) for j in jobs)
+        ws = torch.empty(wsz + 256, dtype=torch.uint8, device=dev)
+        ws = ws[(-ws.data_ptr()) % 256:][:wsz]
+        seq_out = [torch.empty_like(o) for o in plan.outs]
+
+        def sequential():
+            for j, t, o in zip(jobs, tens, seq_out):
+                q2x.run(j.kind, t[0], t[1], t[2], t[3], t[4], None, j.p, precision=prec, out=o, workspace=ws)
+        ms_seq = timed(sequential, 2)
+        same = all(torch.equal(a, b) for a, b in zip(plan.outs, seq_out))
+        results[name] = {"batch_ms": ms_batch, "sequential_ms": ms_seq, "batch_coefficients_per_s": coefs / (ms_batch * 1e-3),
+                         "sequential_coefficients_per_s": coefs / (ms_seq * 1e-3), "speedup": ms_seq / ms_batch,
+                         "batched_equals_sequential": bool(same), "groups": plan.groups,
+                         "capture": "parallel branches" if plan.mode == 1 else "serial"}
+        plan.close()
+        del seq_out
+    out.update(results)
+    out["speedup_batch_fp32_mixed_vs_sequential_fp64"] = results["fp64"]["sequential_ms"] / results["fp32_mixed"]["batch_ms"]
+    return out
+
+
+def error_stats(F, R, elem_norms, density, elem_box, boxes, p):
+    """Scale-aware error max_{b,n} ||dF_{b,n}|| / A_{b,n} (A = sum over the box's elements of
+    |density| * ||F^(e)_n||) and the normwise error ||dF_{b,n}|| / ||F_{b,n}|| (median, max)."""
+    import numpy as np
+    pos = {int(b): i for i, b in enumerate(boxes)}
+    A = np.zeros((len(boxes), p + 1))
+    np.add.at(A, np.array([pos[int(b)] for b in elem_box]), np.abs(density)[:, None] * elem_norms)
+    def deg(X):
+        return np.stack([np.linalg.norm(X[:, n * n:(n + 1) * (n + 1)], axis=1) for n in range(p + 1)], axis=1)
+    dn, rn = deg(F - R), deg(R)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        sa = np.where(A > 0, dn / A, 0.0)
+        nw = np.where(rn > 0, dn / rn, 0.0)
+    return {"scale_aware_max": float(sa.max()), "normwise_median": float(np.median(nw[rn > 0])),
+            "normwise_max": float(nw.max())}
+
+
+def other_workloads(dev, reps=20):
+    """Single calls on the small icosphere (p = 8), the Kuhn tetrahedra and the random-walk segments
+    (p = 12), FP32-mixed and FP64: coefficients/s of the call and of the recursion kernel."""
+    import torch
+
+    from paper_2107_10942_amd import flops, q2x
+    from q2x_inputs import configs
+    out = {}
+    for name, job in (("icosphere_k3_1280_p8_single", configs.sphere_small()),
+                      ("kuhn_tets_511104_p12", configs.kuhn_tet_volume()),
+                      ("random_walk_segments_1000000_p12", configs.random_filaments())):
+        tens = q2x.job_tensors(job, dev)
+        o = torch.empty((job.n_boxes, (job.p + 1) ** 2, 2), dtype=torch.float64, device=dev)
+        res = {"elements": job.n_elems, "boxes": job.n_boxes, "p": job.p}
+        for prec, pn in ((q2x.FP32_MIXED, "fp32_mixed"), (q2x.FP64, "fp64")):
+            ws = q2x.alloc_workspace(job.kind, job.n_elems, job.n_boxes, job.p, prec, device=dev)
+            for _ in range(3):
+                q2x.run(job.kind, *tens, job.p, precision=prec, out=o, workspace=ws)
+            torch.cuda.synchronize()
+            q2x.profile_enable(True)
+            q2x.profile_reset()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                q2x.run(job.kind, *tens, job.p, precision=prec, out=o, workspace=ws)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            rec_ms, call_ms, calls = q2x.profile_read()
+            q2x.profile_enable(False)
+            k = job.kind
+            kern = rec_ms[k] / calls[k]
+            fl = flops.launch_flops(k, job.p, job.n_elems)
+            res[pn] = {"call_ms": dt * 1e3, "kernel_ms": kern,
+                       "coefficients_per_s": job.n_elems * (job.p + 1) ** 2 / dt,
+                       "kernel_tflops": fl / (kern * 1e-3) / 1e12}
+        out[name] = res
+    return out
+
+
+def serving_workload(dev, n_requests, warmup=50, pool_size=24):
+    """Poisson arrivals of requests (perturbed geodesic spheres, N log-uniform in [10k, 2M], p uniform in
+    [8, 24], single/double), meshes in pinned host memory; latency submit -> coefficients in HBM."""
+    import numpy as np
+    import torch
+
+    from paper_2107_10942_amd import q2x, serving
+    from q2x_inputs import configs
+    rng = np.random.default_rng(5)
+    pool = [configs.serving_job(rng) for _ in range(pool_size)]
+    meshes = [serving.pinned_mesh(j) for j in pool]
+    free, _ = torch.cuda.mem_get_info(dev)
+    budget = int(0.75 * free)
+
+    def requests(n, rate, seed):
+        r = np.random.default_rng(seed)
+        arr = serving.poisson_arrivals(n, rate, r) if rate else np.zeros(n)
+        out = []
+        for i in range(n):
+            m = int(r.integers(0, len(meshes)))
+            out.append(serving.Request(kind=int(r.integers(0, 2)), p=int(r.integers(8, 25)), arrival=float(arr[i]),
+                                       **meshes[m]))
+        return out
+
+    srv = serving.Server(dev, hbm_budget=budget, max_batch=16, p_fp32_max=32)
+    srv.serve(requests(20, 0, 1))  # warm-up (library load, allocator)
+    # capacity: a burst of requests all present at t = 0
+    burst = srv.serve(requests(120, 0, 2))
+    capacity = len(burst) / max(r.done for r in burst)
+    out = {"workload": f"{pool_size} perturbed geodesic spheres ({sum(j.n_elems for j in pool)} triangles in all), "
+                       f"N log-uniform [10k, 2M], p uniform [8, 24], single/double; requests draw a mesh, p and kind",
+           "hbm_budget_bytes": budget, "capacity_requests_per_s": capacity,
+           "p_fp32_max": 32, "p_fp32_max_basis": "FP32-mixed meets the 1e-5 scale-aware bar up to p = 32 "
+                                                 "in the parity tests, so no request falls back to FP64"}
+    for load in (0.5, 0.7, 0.9):
+        reqs = srv.serve(requests(warmup + n_requests, load * capacity, 10 + int(10 * load)))[warmup:]
+        summ = serving.latency_summary(reqs)
+        summ["batches"] = srv.stats["batches"]
+        out[f"load_{load}"] = summ
+    return out
 
 
 def coef_complex(t):
@@ -207,18 +365,27 @@ def main():
         line["large_workload"] = {"workload": f"icosphere k=8, {big.n_elems} triangles, level 7, "
                                               f"{big.n_boxes} boxes, single layer, p=16", **lg}
 
+    if not args.no_configs:
+        line["other_workloads"] = other_workloads(dev)
+    if not args.no_batch:
+        line["batch_workload"] = batch_workload(dev)
+    if not args.no_serving:
+        line["serving_workload"] = serving_workload(dev, args.serving_requests)
+
     if not args.no_cpu_baseline:
         import oracle
         nthr = oracle.max_threads()
         # calibrate on every 40th box, then size the sample for ~cpu_seconds
+        refs = {}
+
         def run_sample(stride):
             bx = np.arange(0, B, stride)
             keep = np.isin(single.elem_box, bx)
             ne = int(keep.sum())
             t0 = time.perf_counter()
             for job in (single, double):
-                oracle.q2x(job.kind, p, job.verts, job.elems[keep], job.density[keep], job.elem_box[keep],
-                           job.box_center, boxes=bx)
+                refs[job.kind] = oracle.q2x(job.kind, p, job.verts, job.elems[keep], job.density[keep],
+                                            job.elem_box[keep], job.box_center, boxes=bx)
             return ne, time.perf_counter() - t0, len(bx)
         ne, dt, nbx = run_sample(40)
         rate = 2 * ne / dt  # elements per second (both layers)
@@ -229,6 +396,16 @@ def main():
                                 "kind": "oracle",
                                 "sample": f"every {stride}th box ({nbx} boxes, {ne} triangles) of the same mesh, "
                                           f"single+double layer, p=16, FP64 Gauss/Duffy quadrature, {dt:.1f} s"}
+        # error table of the timed GPU results against the oracle on the same boxes
+        bx = np.arange(0, B, stride)
+        keep = np.isin(single.elem_box, bx)
+        table = {}
+        for name, res in (("fp32_mixed", mixed), ("fp64", plain)):
+            for job, layer in ((single, "single"), (double, "double")):
+                en = oracle.element_norms(job.kind, p, job.verts, job.elems[keep], job.elem_box[keep], job.box_center)
+                table[f"{name}_{layer}"] = error_stats(res[layer][bx], refs[job.kind], en, job.density[keep],
+                                                       job.elem_box[keep], bx, p)
+        line["cpu_baseline"]["error_vs_oracle"] = table
     print(json.dumps(line), flush=True)
 
 

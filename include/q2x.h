@@ -190,20 +190,25 @@ q2x_status q2x_bucket(const int32_t* elem_box, int64_t n_elems, int64_t n_boxes,
  * Q2X_TRI_BOTH).  Q2X_PRESORTED is accepted and has no effect (the batch always
  * sorts); Q2X_ACCUMULATE adds into that job's output.  Results are bitwise the
  * results of the single calls on the same jobs.
- *   q2x_batch_plan     host: checks every job (synchronous errors as for the
- *                      single calls), groups jobs by (kind, precision, order
- *                      bucket), lays out the workspace and copies a small job
- *                      table to the current device (the plan owns it; it is
- *                      freed by q2x_batch_destroy).  The job arrays must stay
- *                      valid while the plan is used; their contents may change
- *                      between runs.
+ *   q2x_batch_plan     host only: checks every job (synchronous errors as for
+ *                      the single calls), groups jobs by (kind, precision,
+ *                      order bucket) and lays out the workspace.  The job
+ *                      arrays must stay valid while the plan is used; their
+ *                      contents may change between runs.
  *   q2x_batch_run      enqueues the batch on `stream`.  The first run on a
- *                      workspace captures the launch sequence in a HIP graph
- *                      (later runs replay it); without Q2X_ACCUMULATE jobs and
- *                      with more than one group, that first run times two
- *                      captures (serial, or group launches as parallel graph
- *                      branches), keeps the faster and synchronises `stream`.
- *                      Calls that share a plan must be ordered on one stream.
+ *                      workspace copies the job tables to a small device
+ *                      buffer owned by the plan (allocated once, freed by
+ *                      q2x_batch_destroy) and captures the launch sequence in
+ *                      a HIP graph; later runs on that workspace replay it.
+ *                      Without Q2X_ACCUMULATE jobs and with more than one
+ *                      group, that first run times two captures (serial, or
+ *                      group launches as parallel graph branches), keeps the
+ *                      faster and synchronises `stream`.  Calls that share a
+ *                      plan must be ordered on one stream.
+ *   q2x_batch_launch   enqueues the batch on `stream` directly, without a
+ *                      graph and without any allocation: the job tables are
+ *                      copied into the workspace on `stream` (for batches that
+ *                      run once, e.g. in serving).
  *   q2x_batch_job_status  q2x_status_get for one job of the last run.
  *   q2x_batch_groups / q2x_batch_mode  number of launch groups; chosen capture
  *                      (0 serial, 1 parallel branches, -1 not run yet).
@@ -227,6 +232,7 @@ typedef struct q2x_plan q2x_plan;
 q2x_status q2x_batch_plan(const q2x_job* jobs, int n_jobs, q2x_plan** plan);
 size_t q2x_batch_workspace_bytes(const q2x_plan* plan);
 q2x_status q2x_batch_run(q2x_plan* plan, void* workspace, size_t workspace_bytes, void* stream);
+q2x_status q2x_batch_launch(q2x_plan* plan, void* workspace, size_t workspace_bytes, void* stream);
 q2x_status q2x_batch_job_status(const q2x_plan* plan, const void* workspace, int job, void* stream,
                                 uint32_t* device_flags, int64_t* n_degenerate, int64_t* n_skipped);
 int q2x_batch_groups(const q2x_plan* plan);

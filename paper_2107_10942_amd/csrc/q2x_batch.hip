@@ -123,16 +123,15 @@ struct q2x_plan {
   std::vector<Group> groups;
   int64_t n_total = 0, total_boxes = 0;
   size_t parts_doubles = 0;
-  // device copies of the tables (allocated by the plan)
-  char* dev = nullptr;
-  BatchJob* d_jobs = nullptr;
-  int64_t* d_elem_base = nullptr;
-  int64_t* d_box_base = nullptr;
-  std::vector<int32_t*> d_gjobs;
-  std::vector<int64_t*> d_gtiles;
+  // job tables: host image; q2x_batch_launch copies it into the workspace, the
+  // graph of q2x_batch_run reads a device copy owned by the plan
+  std::vector<char> table;
+  char* dev_table = nullptr;
+  size_t t_jobs = 0, t_elem_base = 0, t_box_base = 0;  // offsets inside the table
+  std::vector<size_t> t_gjobs, t_gtiles;
   // workspace layout
-  size_t off_status = 0, off_keys = 0, off_sort = 0, off_box_start = 0, off_parts = 0, total = 0;
-  // capture
+  size_t off_table = 0, off_status = 0, off_keys = 0, off_sort = 0, off_box_start = 0, off_parts = 0, total = 0;
+  // graph capture (created on the first q2x_batch_run)
   hipStream_t cap[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<hipEvent_t> evs;
   void* graph_ws = nullptr;
@@ -161,8 +160,12 @@ bool job_ok(const q2x_job& j) {
   return true;
 }
 
-hipError_t enqueue(q2x_plan* P, char* ws, int mode) {
-  hipStream_t s = P->cap[0];
+// the launch sequence on stream s, job tables at tab (mode 1: group launches
+// on the capture streams as parallel branches)
+hipError_t enqueue(q2x_plan* P, char* ws, const char* tab, int mode, hipStream_t s) {
+  const BatchJob* d_jobs = (const BatchJob*)(tab + P->t_jobs);
+  const int64_t* d_elem_base = (const int64_t*)(tab + P->t_elem_base);
+  const int64_t* d_box_base = (const int64_t*)(tab + P->t_box_base);
   Status* st = (Status*)(ws + P->off_status);
   int32_t* keys = (int32_t*)(ws + P->off_keys);
   int32_t* sort_scratch = (int32_t*)(ws + P->off_sort);
@@ -175,7 +178,7 @@ hipError_t enqueue(q2x_plan* P, char* ws, int mode) {
   const int32_t* sperm = nullptr;
   if (P->n_total > 0) {
     const int64_t blocks = std::min<int64_t>((P->n_total + 255) / 256, 65536);
-    hipLaunchKernelGGL(batch_gather_keys, dim3((unsigned)blocks), dim3(256), 0, s, P->d_jobs, P->d_elem_base,
+    hipLaunchKernelGGL(batch_gather_keys, dim3((unsigned)blocks), dim3(256), 0, s, d_jobs, d_elem_base,
                        P->n_jobs, P->n_total, P->total_boxes, keys, st);
     // the sort's own status block (after the jobs') absorbs its invalid-key count
     hipError_t e = bucket_elements(keys, P->n_total, P->total_boxes, sort_scratch, st + P->n_jobs, s, &skeys, &sperm);
@@ -198,9 +201,9 @@ hipError_t enqueue(q2x_plan* P, char* ws, int mode) {
     a.keys = skeys;
     a.perm = sperm;
     a.partials = parts + G.part_off;
-    a.bjobs = P->d_jobs;
-    a.bgroup_jobs = P->d_gjobs[g];
-    a.bgroup_tiles = P->d_gtiles[g];
+    a.bjobs = d_jobs;
+    a.bgroup_jobs = (const int32_t*)(tab + P->t_gjobs[g]);  // (tab: device memory)
+    a.bgroup_tiles = (const int64_t*)(tab + P->t_gtiles[g]);
     a.bng = (int32_t)G.jobs.size();
     a.bstatus = st;
     a.bbox_start = box_start;
@@ -213,7 +216,7 @@ hipError_t enqueue(q2x_plan* P, char* ws, int mode) {
       if (P->groups[g].tiles.back() > 0 && hipStreamWaitEvent(s, ev[1 + g], 0) != hipSuccess) return hipErrorUnknown;
   if (P->total_boxes > 0) {
     const int64_t blocks = std::min<int64_t>((P->total_boxes + 3) / 4, 65536);
-    hipLaunchKernelGGL(batch_fixup, dim3((unsigned)blocks), dim3(256), 0, s, P->d_jobs, P->d_box_base, P->n_jobs,
+    hipLaunchKernelGGL(batch_fixup, dim3((unsigned)blocks), dim3(256), 0, s, d_jobs, d_box_base, P->n_jobs,
                        P->total_boxes, box_start, parts);
   }
   return hipGetLastError();
@@ -221,7 +224,7 @@ hipError_t enqueue(q2x_plan* P, char* ws, int mode) {
 
 hipError_t capture(q2x_plan* P, char* ws, int mode, hipGraph_t* g, hipGraphExec_t* x) {
   if (hipStreamBeginCapture(P->cap[0], hipStreamCaptureModeThreadLocal) != hipSuccess) return hipErrorUnknown;
-  const hipError_t e = enqueue(P, ws, mode);
+  const hipError_t e = enqueue(P, ws, P->dev_table, mode, P->cap[0]);
   hipGraph_t graph = nullptr;
   const hipError_t e2 = hipStreamEndCapture(P->cap[0], &graph);
   if (e != hipSuccess || e2 != hipSuccess) {
@@ -320,7 +323,7 @@ q2x_status q2x_batch_plan(const q2x_job* jobs, int n_jobs, q2x_plan** out) {
   }
   for (BatchJob& J : P->jobs) J.part_off = P->groups[J.group].part_off;
   P->parts_doubles = parts;
-  // workspace layout
+  // workspace layout (the job tables are appended below)
   size_t off = 0;
   P->off_status = off;
   off += align_up((size_t)(n_jobs + 1) * sizeof(Status));
@@ -333,38 +336,31 @@ q2x_status q2x_batch_plan(const q2x_job* jobs, int n_jobs, q2x_plan** out) {
   P->off_parts = off;
   off += align_up(parts * sizeof(double) + 8);
   P->total = off;
-  // device tables, one allocation
-  size_t dbytes = align_up(sizeof(BatchJob) * n_jobs) + 2 * align_up(sizeof(int64_t) * (n_jobs + 1));
-  for (const Group& G : P->groups)
-    dbytes += align_up(sizeof(int32_t) * G.jobs.size()) + align_up(sizeof(int64_t) * G.tiles.size());
-  if (hipMalloc((void**)&P->dev, dbytes) != hipSuccess) {
-    delete P;
-    return Q2X_ERR_HIP;
-  }
-  std::vector<char> host(dbytes, 0);
-  size_t o = 0;
-  auto place = [&](const void* src, size_t n) {
-    memcpy(host.data() + o, src, n);
-    char* d = P->dev + o;
-    o += align_up(n);
-    return d;
+  // job tables (host image)
+  size_t tb = 0;
+  auto reserve = [&](size_t n) {
+    const size_t o = tb;
+    tb += align_up(n);
+    return o;
   };
-  P->d_jobs = (BatchJob*)place(P->jobs.data(), sizeof(BatchJob) * n_jobs);
-  P->d_elem_base = (int64_t*)place(P->elem_base.data(), sizeof(int64_t) * (n_jobs + 1));
-  P->d_box_base = (int64_t*)place(P->box_base.data(), sizeof(int64_t) * (n_jobs + 1));
+  P->t_jobs = reserve(sizeof(BatchJob) * n_jobs);
+  P->t_elem_base = reserve(sizeof(int64_t) * (n_jobs + 1));
+  P->t_box_base = reserve(sizeof(int64_t) * (n_jobs + 1));
   for (const Group& G : P->groups) {
-    P->d_gjobs.push_back((int32_t*)place(G.jobs.data(), sizeof(int32_t) * G.jobs.size()));
-    P->d_gtiles.push_back((int64_t*)place(G.tiles.data(), sizeof(int64_t) * G.tiles.size()));
+    P->t_gjobs.push_back(reserve(sizeof(int32_t) * G.jobs.size()));
+    P->t_gtiles.push_back(reserve(sizeof(int64_t) * G.tiles.size()));
   }
-  bool ok = hipMemcpy(P->dev, host.data(), dbytes, hipMemcpyHostToDevice) == hipSuccess;
-  for (int i = 0; i < 4 && ok; ++i) ok = hipStreamCreateWithFlags(&P->cap[i], hipStreamNonBlocking) == hipSuccess;
-  P->evs.resize(P->groups.size() + 1, nullptr);
-  for (auto& e : P->evs)
-    if (ok) ok = hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
-  if (!ok) {
-    q2x_batch_destroy(P);
-    return Q2X_ERR_HIP;
+  P->table.assign(tb, 0);
+  memcpy(P->table.data() + P->t_jobs, P->jobs.data(), sizeof(BatchJob) * n_jobs);
+  memcpy(P->table.data() + P->t_elem_base, P->elem_base.data(), sizeof(int64_t) * (n_jobs + 1));
+  memcpy(P->table.data() + P->t_box_base, P->box_base.data(), sizeof(int64_t) * (n_jobs + 1));
+  for (size_t g = 0; g < P->groups.size(); ++g) {
+    const Group& G = P->groups[g];
+    memcpy(P->table.data() + P->t_gjobs[g], G.jobs.data(), sizeof(int32_t) * G.jobs.size());
+    memcpy(P->table.data() + P->t_gtiles[g], G.tiles.data(), sizeof(int64_t) * G.tiles.size());
   }
+  P->off_table = P->total;
+  P->total += align_up(tb);
   // signature of the launch shapes (autotune cache key)
   std::string sig;
   for (const Group& G : P->groups)
@@ -389,6 +385,19 @@ q2x_status q2x_batch_run(q2x_plan* plan, void* workspace, size_t workspace_bytes
   if (plan->exec && plan->graph_ws == workspace)
     return hipGraphLaunch(plan->exec, s) == hipSuccess ? Q2X_OK : Q2X_ERR_HIP;
   drop_graph(plan);
+  if (!plan->cap[0]) {
+    bool ok = true;
+    for (int i = 0; i < 4 && ok; ++i) ok = hipStreamCreateWithFlags(&plan->cap[i], hipStreamNonBlocking) == hipSuccess;
+    plan->evs.resize(plan->groups.size() + 1, nullptr);
+    for (auto& e : plan->evs)
+      if (ok) ok = hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+    if (!ok) return Q2X_ERR_HIP;
+  }
+  if (!plan->dev_table) {  // the graph's job tables: a device copy owned by the plan
+    if (hipMalloc((void**)&plan->dev_table, plan->table.size()) != hipSuccess) return Q2X_ERR_HIP;
+    if (hipMemcpy(plan->dev_table, plan->table.data(), plan->table.size(), hipMemcpyHostToDevice) != hipSuccess)
+      return Q2X_ERR_HIP;
+  }
   int mode = 0;
   bool tuned = false;
   {
@@ -445,6 +454,17 @@ q2x_status q2x_batch_run(q2x_plan* plan, void* workspace, size_t workspace_bytes
   return hipGraphLaunch(plan->exec, s) == hipSuccess ? Q2X_OK : Q2X_ERR_HIP;
 }
 
+q2x_status q2x_batch_launch(q2x_plan* plan, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!plan) return Q2X_ERR_ARG;
+  if (!workspace || ((uintptr_t)workspace % kAlign) != 0 || workspace_bytes < plan->total) return Q2X_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  if (hipMemcpyAsync(ws + plan->off_table, plan->table.data(), plan->table.size(), hipMemcpyHostToDevice, s) !=
+      hipSuccess)
+    return Q2X_ERR_HIP;
+  return enqueue(plan, ws, ws + plan->off_table, 0, s) == hipSuccess ? Q2X_OK : Q2X_ERR_HIP;
+}
+
 q2x_status q2x_batch_job_status(const q2x_plan* plan, const void* workspace, int job, void* stream,
                                 uint32_t* device_flags, int64_t* n_degenerate, int64_t* n_skipped) {
   if (!plan || !workspace || job < 0 || job >= plan->n_jobs) return Q2X_ERR_ARG;
@@ -459,7 +479,7 @@ void q2x_batch_destroy(q2x_plan* plan) {
     if (e) (void)hipEventDestroy(e);
   for (auto& c : plan->cap)
     if (c) (void)hipStreamDestroy(c);
-  if (plan->dev) (void)hipFree(plan->dev);
+  if (plan->dev_table) (void)hipFree(plan->dev_table);
   delete plan;
 }
 

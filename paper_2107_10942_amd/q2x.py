@@ -26,7 +26,7 @@ P_MAX = 32
 FLAG_BAD_BOX, FLAG_NONFINITE, FLAG_RESERVED, FLAG_BAD_VERTEX, FLAG_NOT_SORTED = 1, 2, 4, 8, 16
 EXPORTS = ("q2x_workspace_bytes", "q2x_bucket_workspace_bytes", "q2x_bucket", "q2x_tri_single", "q2x_tri_double", "q2x_segment", "q2x_tet",
            "q2x_tri_both", "q2x_status_get", "q2x_status_string", "q2x_profile_enable", "q2x_profile_reset",
-           "q2x_profile_read", "q2x_version", "q2x_batch_plan", "q2x_batch_workspace_bytes", "q2x_batch_run",
+           "q2x_profile_read", "q2x_version", "q2x_batch_plan", "q2x_batch_workspace_bytes", "q2x_batch_run", "q2x_batch_launch",
            "q2x_batch_job_status", "q2x_batch_groups", "q2x_batch_mode", "q2x_batch_destroy")
 
 
@@ -85,6 +85,8 @@ def lib():
         L.q2x_batch_workspace_bytes.restype = sz
         L.q2x_batch_run.argtypes = [vp, vp, sz, vp]
         L.q2x_batch_run.restype = ci
+        L.q2x_batch_launch.argtypes = [vp, vp, sz, vp]
+        L.q2x_batch_launch.restype = ci
         L.q2x_batch_job_status.argtypes = [vp, vp, ci, vp, ctypes.POINTER(ctypes.c_uint32),
                                            ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
         L.q2x_batch_job_status.restype = ci
@@ -264,6 +266,14 @@ class BatchPlan:
             workspace = self.workspace if self.workspace is not None else self.alloc_workspace()
         _check(lib().q2x_batch_run(self._h, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
                                    _stream(stream)))
+        return self.outs
+
+    def launch(self, workspace=None, stream=None):
+        """Enqueue once, without a graph (q2x_batch_launch)."""
+        if workspace is None:
+            workspace = self.workspace if self.workspace is not None else self.alloc_workspace()
+        _check(lib().q2x_batch_launch(self._h, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                      _stream(stream)))
         return self.outs
 
     def status(self, j, workspace=None, stream=None):
