@@ -163,6 +163,30 @@ def other_workloads(dev, reps=20):
                        "coefficients_per_s": job.n_elems * (job.p + 1) ** 2 / dt,
                        "kernel_tflops": fl / (kern * 1e-3) / 1e12}
         out[name] = res
+    # the random walks again with a vector density (walk tangent x strength): three outputs, one recursion
+    import numpy as np
+    job = configs.random_filaments()
+    t = job.verts[job.elems[:, 1]] - job.verts[job.elems[:, 0]]
+    t /= np.linalg.norm(t, axis=1, keepdims=True)
+    d3 = torch.as_tensor(t * np.random.default_rng(5).uniform(-1, 1, (job.n_elems, 1)), dtype=torch.float64,
+                         device=dev).contiguous()
+    tens = q2x.job_tensors(job, dev)
+    o3 = torch.empty((3, job.n_boxes, (job.p + 1) ** 2, 2), dtype=torch.float64, device=dev)
+    res = {"elements": job.n_elems, "boxes": job.n_boxes, "p": job.p, "outputs": 3}
+    for prec, pn in ((q2x.FP32_MIXED, "fp32_mixed"), (q2x.FP64, "fp64")):
+        ws = q2x.alloc_workspace(q2x.SEGMENT_VEC, job.n_elems, job.n_boxes, job.p, prec, device=dev)
+        call = lambda: q2x.segment_vec(tens[0], tens[1], d3, tens[3], tens[4], None, job.p,  # noqa: E731
+                                       precision=prec, out=o3, workspace=ws)
+        for _ in range(3):
+            call()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            call()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        res[pn] = {"call_ms": dt * 1e3, "coefficients_per_s": 3 * job.n_elems * (job.p + 1) ** 2 / dt}
+    out["random_walk_segments_vector_density_1000000_p12"] = res
     return out
 
 

@@ -75,7 +75,8 @@ typedef enum {
   Q2X_TRI_DOUBLE = 1,
   Q2X_SEGMENT = 2,
   Q2X_TET = 3,
-  Q2X_TRI_BOTH = 4 /* single + double layer of one triangle mesh (q2x_tri_both) */
+  Q2X_TRI_BOTH = 4,   /* single + double layer of one triangle mesh (q2x_tri_both) */
+  Q2X_SEGMENT_VEC = 5 /* segments with a vector density, three outputs (q2x_segment_vec) */
 } q2x_kind;
 typedef enum { Q2X_FP64 = 0, Q2X_FP32_MIXED = 1 } q2x_precision;
 typedef enum { Q2X_NORM_FMM = 0, Q2X_NORM_MOMENT = 1 } q2x_norm;
@@ -157,6 +158,21 @@ q2x_status q2x_segment(const double* verts, int64_t n_verts, const int32_t* segs
                        void* stream);
 
 /*
+ * Segments with a constant VECTOR line density (the integrals K of Sec. 2,
+ * Eq. (3), all three components, as in Biot-Savart vortex filaments): one
+ * recursion per segment (as q2x_segment) and three outputs, component c with
+ * density density3[e][c].  Equal bitwise to three q2x_segment calls with the
+ * component densities.
+ *   segs     [n_segs][2] int32; density3 [n_segs][3] double
+ *   coeffs3  [3][n_boxes][(p+1)^2][2] double (component-major)
+ * Workspace: q2x_workspace_bytes(Q2X_SEGMENT_VEC, ...).  Other arguments as above.
+ */
+q2x_status q2x_segment_vec(const double* verts, int64_t n_verts, const int32_t* segs, int64_t n_segs,
+                           const double* density3, const int32_t* elem_box, const double* box_center,
+                           const double* box_radius, int64_t n_boxes, int p, int precision, int norm, unsigned flags,
+                           double* coeffs3, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
  * Tetrahedra with constant charge (the volume integrals N of Sec. 2, Eq. (4);
  * Sec. 3.2, Eqs. (14),(20)).  Recursion: q at x2, j along x3->x2, face
  * integrals b coned from x4 (Lemma 5, Eq. (38)), volume integrals a coned from
@@ -187,7 +203,7 @@ q2x_status q2x_bucket(const int32_t* elem_box, int64_t n_elems, int64_t n_boxes,
 /*
  * Batches: many meshes (jobs) in one replayed launch sequence.  A job is one
  * single call's arguments; kind may be any q2x_kind (density2/coeffs2 only for
- * Q2X_TRI_BOTH).  Q2X_PRESORTED is accepted and has no effect (the batch always
+ * Q2X_TRI_BOTH; for Q2X_SEGMENT_VEC density is [N][3] and coeffs [3][B][..]).  Q2X_PRESORTED is accepted and has no effect (the batch always
  * sorts); Q2X_ACCUMULATE adds into that job's output.  Results are bitwise the
  * results of the single calls on the same jobs.
  *   q2x_batch_plan     host only: checks every job (synchronous errors as for
@@ -255,7 +271,7 @@ const char* q2x_status_string(int status);
  * Kernel timing for measurement.  When enabled, each call records HIP events
  * on its own stream around its recursion kernel and around the whole call;
  * q2x_profile_read synchronises those events and returns, per element kind
- * (arrays of 5 indexed by q2x_kind), the summed recursion-kernel time (ms),
+ * (arrays of 6 indexed by q2x_kind), the summed recursion-kernel time (ms),
  * the summed whole-call time (ms, bucketing and fix-up included) and the
  * number of calls since the last reset.  Any output pointer may be NULL.
  */

@@ -1,7 +1,7 @@
 """Build the gfx950 Q2X library (``libq2x.so``) in-tree with hipcc.
 
-Every HIP source is compiled for gfx950 only.  The ten tile-kernel
-instantiation units (5 element kinds x 2 precisions) are large, fully
+Every HIP source is compiled for gfx950 only.  The twelve tile-kernel
+instantiation units (6 element kinds x 2 precisions) are large, fully
 unrolled translation units, so they compile in parallel.
 """
 from __future__ import annotations
@@ -23,7 +23,7 @@ COMMON = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",
           "-I", os.path.join(HERE, "..", "include")]
 
 SIMPLE = ["q2x_api.hip", "q2x_bucket.hip", "q2x_dispatch.hip", "q2x_batch.hip"]
-INST = [(k, f) for k in range(5) for f in (0, 1)]
+INST = [(k, f) for k in range(6) for f in (0, 1)]
 
 
 def _units():

@@ -28,8 +28,7 @@ __global__ __launch_bounds__(256) void q2x_fixup_kernel(FixupArgs f) {
   const int64_t ncoef = (int64_t)(f.p + 1) * (f.p + 1);
   for (int64_t b = wave; b < f.n_boxes; b += nwaves) {
     const int64_t s = f.n_pos ? f.box_start[b] : 0, t = f.n_pos ? f.box_start[b + 1] : 0;
-    fixup_box(lane, s, t, 0, 0, f.partials, f.coeffs + b * ncoef * 2, f.coeffs2 ? f.coeffs2 + b * ncoef * 2 : nullptr,
-              f.nout, f.p, f.P, f.norm, f.accumulate);
+    fixup_box(lane, s, t, 0, 0, f.partials, f.outs, b, f.nout, f.p, f.P, f.norm, f.accumulate);
   }
 }
 
@@ -58,8 +57,8 @@ Layout layout(int64_t n, int64_t nb, int P, int nout) {
   return L;
 }
 
-constexpr int kKinds = 5;
-int outputs_per_kind(int kind) { return kind == Q2X_TRI_BOTH ? 2 : 1; }
+constexpr int kKinds = 6;
+int outputs_per_kind(int kind) { return kind == Q2X_TRI_BOTH ? 2 : (kind == Q2X_SEGMENT_VEC ? 3 : 1); }
 
 // ---- kernel timing (measurement aid)
 struct Prof {
@@ -92,10 +91,12 @@ Prof::Ev get_ev() {
   return e;
 }
 
+// One call.  Output o (o < outputs of the kind) takes its density from
+// dens[o][e * dstride] and writes outs[o].
 q2x_status run(int kind, const double* verts, int64_t n_verts, const int32_t* elems, int64_t n_elems,
-               const double* density, const double* density2, const int32_t* elem_box, const double* box_center,
+               const double* const* dens, int dstride, const int32_t* elem_box, const double* box_center,
                const double* box_radius, int64_t n_boxes, int p, int prec, int norm, unsigned flags,
-               double* coeffs, double* coeffs2, void* workspace, size_t workspace_bytes, void* stream) {
+               double* const* outs, void* workspace, size_t workspace_bytes, void* stream) {
   const int nout = outputs_per_kind(kind);
   if (p < 0 || p > Q2X_P_MAX) return Q2X_ERR_P_RANGE;
   if (n_verts < 0 || n_elems < 0 || n_boxes < 0 || n_elems >= ((int64_t)1 << 31) - 64 ||
@@ -106,20 +107,19 @@ q2x_status run(int kind, const double* verts, int64_t n_verts, const int32_t* el
   if (flags & ~(unsigned)(Q2X_ACCUMULATE | Q2X_PRESORTED)) return Q2X_ERR_ARG;
   if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return Q2X_ERR_WORKSPACE;
   (void)box_radius;  // accepted for interface compatibility; not read (see q2x.h)
-  if (n_boxes > 0 && (!coeffs || !box_center)) return Q2X_ERR_ARG;
-  if (n_elems > 0 && (!verts || !elems || !density || !elem_box)) return Q2X_ERR_ARG;
-  if (((uintptr_t)coeffs % 8) || ((uintptr_t)verts % 8) || ((uintptr_t)density % 8) ||
-      ((uintptr_t)box_center % 8) || ((uintptr_t)elems % 4) ||
-      ((uintptr_t)elem_box % 4))
+  if (n_boxes > 0 && !box_center) return Q2X_ERR_ARG;
+  if (n_elems > 0 && (!verts || !elems || !elem_box)) return Q2X_ERR_ARG;
+  if (((uintptr_t)verts % 8) || ((uintptr_t)box_center % 8) || ((uintptr_t)elems % 4) || ((uintptr_t)elem_box % 4))
     return Q2X_ERR_ARG;
-  if (nout == 2) {
-    if (n_boxes > 0 && !coeffs2) return Q2X_ERR_ARG;
-    if (n_elems > 0 && !density2) return Q2X_ERR_ARG;
-    if (((uintptr_t)coeffs2 % 8) || ((uintptr_t)density2 % 8)) return Q2X_ERR_ARG;
-    // the two outputs must not overlap
-    const size_t out_bytes = (size_t)n_boxes * (size_t)(p + 1) * (size_t)(p + 1) * 2 * sizeof(double);
-    const uintptr_t c1 = (uintptr_t)coeffs, c2 = (uintptr_t)coeffs2;
-    if (n_boxes > 0 && c1 < c2 + out_bytes && c2 < c1 + out_bytes) return Q2X_ERR_ARG;
+  const size_t out_bytes = (size_t)n_boxes * (size_t)(p + 1) * (size_t)(p + 1) * 2 * sizeof(double);
+  for (int o = 0; o < nout; ++o) {
+    if (n_boxes > 0 && !outs[o]) return Q2X_ERR_ARG;
+    if (n_elems > 0 && !dens[o]) return Q2X_ERR_ARG;
+    if (((uintptr_t)outs[o] % 8) || ((uintptr_t)dens[o] % 8)) return Q2X_ERR_ARG;
+    for (int q = 0; q < o; ++q) {  // outputs must not overlap
+      const uintptr_t c1 = (uintptr_t)outs[q], c2 = (uintptr_t)outs[o];
+      if (n_boxes > 0 && c1 < c2 + out_bytes && c2 < c1 + out_bytes) return Q2X_ERR_ARG;
+    }
   }
   const int P = bucket_order(p);
   if (P < 0) return Q2X_ERR_UNSUPPORTED;
@@ -158,14 +158,13 @@ q2x_status run(int kind, const double* verts, int64_t n_verts, const int32_t* el
   TileArgs a{};
   a.verts = verts;
   a.elems = elems;
-  a.density = density;
-  a.density2 = (nout == 2) ? density2 : nullptr;
+  for (int o = 0; o < nout; ++o) a.dens[o] = dens[o];
+  a.dstride = dstride;
   a.keys = keys;
   a.perm = perm;
   a.box_center = box_center;
   a.box_start = box_start;
-  a.coeffs = coeffs;
-  a.coeffs2 = (nout == 2) ? coeffs2 : nullptr;
+  for (int o = 0; o < nout; ++o) a.outs[o] = outs[o];
   a.partials = partials;
   a.status = st;
   a.n_verts = n_verts;
@@ -182,12 +181,11 @@ q2x_status run(int kind, const double* verts, int64_t n_verts, const int32_t* el
   }
   if (timing) hipEventRecord(ev.c, s);
   if (n_boxes > 0) {
-    FixupArgs f;
+    FixupArgs f{};
     f.box_start = box_start;
     f.partials = partials;
     f.n_pos = n_elems;
-    f.coeffs = coeffs;
-    f.coeffs2 = a.coeffs2;
+    for (int o = 0; o < nout; ++o) f.outs[o] = outs[o];
     f.n_boxes = n_boxes;
     f.p = p;
     f.P = P;
@@ -229,8 +227,10 @@ size_t q2x_workspace_bytes(int kind, int64_t n_elems, int64_t n_boxes, int p, in
                   const int32_t* elem_box, const double* box_center, const double* box_radius, int64_t n_boxes,  \
                   int p, int precision, int norm, unsigned flags, double* coeffs, void* workspace,                \
                   size_t workspace_bytes, void* stream) {                                                         \
-    return run(KIND, verts, n_verts, el, n_el, density, nullptr, elem_box, box_center, box_radius, n_boxes, p,    \
-               precision, norm, flags, coeffs, nullptr, workspace, workspace_bytes, stream);                      \
+    const double* dens[1] = {density};                                                                           \
+    double* outs[1] = {coeffs};                                                                                    \
+    return run(KIND, verts, n_verts, el, n_el, dens, 1, elem_box, box_center, box_radius, n_boxes, p, precision,  \
+               norm, flags, outs, workspace, workspace_bytes, stream);                                            \
   }
 
 Q2X_ENTRY(q2x_tri_single, Q2X_TRI_SINGLE)
@@ -243,9 +243,23 @@ q2x_status q2x_tri_both(const double* verts, int64_t n_verts, const int32_t* tri
                         const double* box_center, const double* box_radius, int64_t n_boxes, int p,
                         int precision, int norm, unsigned flags, double* coeffs_single, double* coeffs_double,
                         void* workspace, size_t workspace_bytes, void* stream) {
-  return run(Q2X_TRI_BOTH, verts, n_verts, tris, n_tris, density_single, density_double, elem_box, box_center,
-             box_radius, n_boxes, p, precision, norm, flags, coeffs_single, coeffs_double, workspace,
-             workspace_bytes, stream);
+  const double* dens[2] = {density_single, density_double};
+  double* outs[2] = {coeffs_single, coeffs_double};
+  return run(Q2X_TRI_BOTH, verts, n_verts, tris, n_tris, dens, 1, elem_box, box_center, box_radius, n_boxes, p,
+             precision, norm, flags, outs, workspace, workspace_bytes, stream);
+}
+
+q2x_status q2x_segment_vec(const double* verts, int64_t n_verts, const int32_t* segs, int64_t n_segs,
+                           const double* density3, const int32_t* elem_box, const double* box_center,
+                           const double* box_radius, int64_t n_boxes, int p, int precision, int norm, unsigned flags,
+                           double* coeffs3, void* workspace, size_t workspace_bytes, void* stream) {
+  if (p < 0 || p > Q2X_P_MAX) return Q2X_ERR_P_RANGE;
+  if (n_boxes < 0) return Q2X_ERR_ARG;
+  const int64_t plane = n_boxes * (int64_t)(p + 1) * (p + 1) * 2;  // doubles per component
+  const double* dens[3] = {density3, density3 ? density3 + 1 : nullptr, density3 ? density3 + 2 : nullptr};
+  double* outs[3] = {coeffs3, coeffs3 ? coeffs3 + plane : nullptr, coeffs3 ? coeffs3 + 2 * plane : nullptr};
+  return run(Q2X_SEGMENT_VEC, verts, n_verts, segs, n_segs, dens, 3, elem_box, box_center, box_radius, n_boxes, p,
+             precision, norm, flags, outs, workspace, workspace_bytes, stream);
 }
 
 size_t q2x_bucket_workspace_bytes(int64_t n_elems, int64_t n_boxes) {

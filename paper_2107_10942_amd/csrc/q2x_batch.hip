@@ -87,10 +87,8 @@ __global__ __launch_bounds__(256) void batch_fixup(const BatchJob* __restrict__ 
     }
     const BatchJob& J = jobs[lo];
     const int64_t b = gb - J.box_base;
-    const int64_t ncoef = (int64_t)(J.p + 1) * (J.p + 1);
-    fixup_box(lane, box_start[gb], box_start[gb + 1], box_start[J.box_base], J.tile_base, parts + J.part_off,
-              J.coeffs + b * ncoef * 2, J.coeffs2 ? J.coeffs2 + b * ncoef * 2 : nullptr, J.nout, J.p, J.P, J.norm,
-              J.accumulate);
+    fixup_box(lane, box_start[gb], box_start[gb + 1], box_start[J.box_base], J.tile_base, parts + J.part_off, J.outs,
+              b, J.nout, J.p, J.P, J.norm, J.accumulate);
   }
 }
 
@@ -144,7 +142,7 @@ struct q2x_plan {
 namespace {
 
 bool job_ok(const q2x_job& j) {
-  if (j.kind < Q2X_TRI_SINGLE || j.kind > Q2X_TRI_BOTH) return false;
+  if (j.kind < Q2X_TRI_SINGLE || j.kind > Q2X_SEGMENT_VEC) return false;
   if (j.p < 0 || j.p > Q2X_P_MAX || bucket_order(j.p) < 0) return false;
   if (j.precision != Q2X_FP64 && j.precision != Q2X_FP32_MIXED) return false;
   if (j.norm != Q2X_NORM_FMM && j.norm != Q2X_NORM_MOMENT) return false;
@@ -276,7 +274,7 @@ q2x_status q2x_batch_plan(const q2x_job* jobs, int n_jobs, q2x_plan** out) {
       G.kind = q.kind;
       G.prec = q.precision;
       G.P = Pb;
-      G.nout = (q.kind == Q2X_TRI_BOTH) ? 2 : 1;
+      G.nout = (q.kind == Q2X_TRI_BOTH) ? 2 : (q.kind == Q2X_SEGMENT_VEC ? 3 : 1);
       G.tiles.push_back(0);
       G.part_off = 0;
       P->groups.push_back(G);
@@ -286,12 +284,22 @@ q2x_status q2x_batch_plan(const q2x_job* jobs, int n_jobs, q2x_plan** out) {
     J = BatchJob{};
     J.verts = q.verts;
     J.elems = q.elems;
-    J.density = q.density;
-    J.density2 = (q.kind == Q2X_TRI_BOTH) ? q.density2 : nullptr;
+    const int64_t plane = q.n_boxes * (int64_t)(q.p + 1) * (q.p + 1) * 2;
+    J.dstride = 1;
+    J.dens[0] = q.density;
+    J.outs[0] = q.coeffs;
+    if (q.kind == Q2X_TRI_BOTH) {
+      J.dens[1] = q.density2;
+      J.outs[1] = q.coeffs2;
+    } else if (q.kind == Q2X_SEGMENT_VEC) {  // density [N][3], coefficients [3][B][(p+1)^2][2]
+      J.dstride = 3;
+      J.dens[1] = q.density ? q.density + 1 : nullptr;
+      J.dens[2] = q.density ? q.density + 2 : nullptr;
+      J.outs[1] = q.coeffs ? q.coeffs + plane : nullptr;
+      J.outs[2] = q.coeffs ? q.coeffs + 2 * plane : nullptr;
+    }
     J.elem_box = q.elem_box;
     J.box_center = q.box_center;
-    J.coeffs = q.coeffs;
-    J.coeffs2 = (q.kind == Q2X_TRI_BOTH) ? q.coeffs2 : nullptr;
     J.n_verts = q.n_verts;
     J.n_elems = q.n_elems;
     J.n_boxes = q.n_boxes;

@@ -14,6 +14,8 @@ Q2X_DECL(3, 0)
 Q2X_DECL(3, 1)
 Q2X_DECL(4, 0)
 Q2X_DECL(4, 1)
+Q2X_DECL(5, 0)
+Q2X_DECL(5, 1)
 #undef Q2X_DECL
 
 // Compiled orders.  A request for order p runs the smallest bucket P >= p:
@@ -40,6 +42,8 @@ hipError_t launch_tiles(int kind, int prec, int P, const TileArgs& a, int64_t n_
     case 7: return launch_tiles_k3_f32_1(P, a, n_tiles, s);
     case 8: return launch_tiles_k4_f32_0(P, a, n_tiles, s);
     case 9: return launch_tiles_k4_f32_1(P, a, n_tiles, s);
+    case 10: return launch_tiles_k5_f32_0(P, a, n_tiles, s);
+    case 11: return launch_tiles_k5_f32_1(P, a, n_tiles, s);
     default: return hipErrorInvalidValue;
   }
 }

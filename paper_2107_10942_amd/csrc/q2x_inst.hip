@@ -1,7 +1,7 @@
 // q2x_inst.hip -- instantiates the tile kernel for one (kind, precision) pair
 // and every compiled order bucket.  Built once per pair with
-// -DQ2X_INST_KIND=<q2x_kind> -DQ2X_INST_F32=<0|1> so the ten large unrolled
-// translation units compile in parallel (five kinds x two precisions).
+// -DQ2X_INST_KIND=<q2x_kind> -DQ2X_INST_F32=<0|1> so the twelve large unrolled
+// translation units compile in parallel (six kinds x two precisions).
 #include "q2x_tile.hpp"
 
 #ifndef Q2X_INST_KIND

@@ -35,14 +35,13 @@ struct BatchJob;
 struct TileArgs {
   const double* verts;
   const int32_t* elems;
-  const double* density;
-  const double* density2;    // second output's density (two-output kinds), else nullptr
+  const double* dens[3];     // density of output o (unused entries nullptr); element e at dens[o][e * dstride]
+  int32_t dstride;
   const int32_t* keys;       // box id of each sorted position (elem_box itself when presorted)
   const int32_t* perm;       // sorted position -> element index (nullptr: identity)
   const double* box_center;
   int32_t* box_start;        // [n_boxes + 1] out: start position of each box
-  double* coeffs;            // [n_boxes][(p+1)^2][2]
-  double* coeffs2;           // second output (two-output kinds), else nullptr
+  double* outs[3];           // coefficients of output o: [n_boxes][(p+1)^2][2]
   double* partials;          // [n_tiles][2][nout][tri(P+1)][2] raw sums of boxes cut by tile edges
   Status* status;
   int64_t n_verts;
@@ -64,31 +63,28 @@ struct TileArgs {
 struct BatchJob {
   const double* verts;
   const int32_t* elems;
-  const double* density;
-  const double* density2;
+  const double* dens[3];
   const int32_t* elem_box;
   const double* box_center;
-  double* coeffs;
-  double* coeffs2;
+  double* outs[3];
   int64_t n_verts, n_elems, n_boxes;
   int64_t elem_base;   // first element in the concatenation of all jobs
   int64_t box_base;    // first global box id
   int64_t tile_base;   // first tile of the job within its group's launch
   int64_t part_off;    // offset (doubles) of the job's group partials in the workspace
-  int32_t kind, prec, P, p, norm, accumulate, nout, group;
+  int32_t kind, prec, P, p, norm, accumulate, nout, group, dstride;
 };
 
 // Arguments of the fix-up kernel (boxes cut by tile edges, empty boxes).
 struct FixupArgs {
   const int32_t* box_start;  // written by the tile kernel (unused when n_pos == 0)
   const double* partials;
-  double* coeffs;
-  double* coeffs2;
+  double* outs[3];
   int64_t n_pos;
   int64_t n_boxes;
   int p;
   int P;                     // bucket order the partials were laid out for
-  int nout;                  // outputs per element kind (1, or 2 for Q2X_TRI_BOTH)
+  int nout;                  // outputs per element kind (1; 2 for Q2X_TRI_BOTH; 3 for Q2X_SEGMENT_VEC)
   int norm;
   int accumulate;
 };
@@ -162,13 +158,14 @@ __device__ __forceinline__ void tri_nm(int g, int& n, int& m) {
 // whose tiles start at position base; tiles numbered from tile0), finalise
 // and store.  Empty boxes get zeros unless accumulating.  One wavefront.
 __device__ __forceinline__ void fixup_box(int lane, int64_t s, int64_t t, int64_t base, int64_t tile0,
-                                          const double* partials, double* c0, double* c1, int nout, int p, int P,
-                                          int norm, int accumulate) {
+                                          const double* partials, double* const* outs, int64_t b, int nout, int p,
+                                          int P, int norm, int accumulate) {
   const int ncoef = (p + 1) * (p + 1);
+  auto row_of = [&](int o) { return outs[o] + b * (int64_t)ncoef * 2; };
   if (t <= s) {
     if (!accumulate)
       for (int o = 0; o < nout; ++o) {
-        double* row = o ? c1 : c0;
+        double* row = row_of(o);
         for (int i = lane; i < 2 * ncoef; i += 64) row[i] = 0.0;
       }
     return;
@@ -190,7 +187,7 @@ __device__ __forceinline__ void fixup_box(int lane, int64_t s, int64_t t, int64_
     }
     int n, m;
     tri_nm(g, n, m);
-    finalize_store(o ? c1 : c0, n, m, ar, ai, norm, accumulate);
+    finalize_store(row_of(o), n, m, ar, ai, norm, accumulate);
   }
 }
 

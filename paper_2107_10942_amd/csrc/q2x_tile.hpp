@@ -195,6 +195,23 @@ struct KindInfo<Q2X_TRI_BOTH> {  // output 0 single layer, output 1 double layer
   static constexpr int depth(int o) { return o == 1 ? 1 : 2; }
   static constexpr int slot(int o) { return o == 1 ? 0 : 1; }  // l~_n (from degree n-1) before i~_n
 };
+template <>
+struct KindInfo<Q2X_SEGMENT_VEC> {  // the segment chain; three outputs, one per density component
+  static constexpr int nv = 2, nch = 2, nout = 3;
+  static constexpr int vert(int k) { return k == 0 ? 1 : 0; }
+  static constexpr bool dbl(int) { return false; }
+  static constexpr int shift(int) { return 0; }
+  static constexpr int depth(int) { return 1; }
+  static constexpr int slot(int o) { return o; }
+};
+
+// output staged in slot s of a degree (inverse of KindInfo::slot)
+template <typename KI>
+__host__ __device__ constexpr int out_of_slot(int s) {
+  for (int o = 0; o < KI::nout; ++o)
+    if (KI::slot(o) == s) return o;
+  return 0;
+}
 
 template <typename T>
 struct PrecInfo;
@@ -258,11 +275,14 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
     const BatchJob& J = a.bjobs[jid];
     a.verts = J.verts;
     a.elems = J.elems;
-    a.density = J.density;
-    a.density2 = J.density2;
+    a.dens[0] = J.dens[0];
+    a.dens[1] = J.dens[1];
+    a.dens[2] = J.dens[2];
+    a.dstride = J.dstride;
     a.box_center = J.box_center;
-    a.coeffs = J.coeffs;
-    a.coeffs2 = J.coeffs2;
+    a.outs[0] = J.outs[0];
+    a.outs[1] = J.outs[1];
+    a.outs[2] = J.outs[2];
     a.status = a.bstatus + jid;
     a.n_verts = J.n_verts;
     a.n_boxes = J.n_boxes;
@@ -306,8 +326,8 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
         xv[k][2] = a.verts[3 * (int64_t)vi + 2];
       }
     }
-    sigma[0] = a.density[e];
-    if constexpr (NOUT == 2) sigma[1] = a.density2[e];
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) sigma[o] = a.dens[o][e * a.dstride];
     cx = a.box_center[3 * (int64_t)key];
     cy = a.box_center[3 * (int64_t)key + 1];
     cz = a.box_center[3 * (int64_t)key + 2];
@@ -327,13 +347,14 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
   double J = 0.0, nx = 0.0, ny = 0.0, nz = 0.0;
   if (ok) {
     const double ux = xv[1][0] - xv[0][0], uy = xv[1][1] - xv[0][1], uz = xv[1][2] - xv[0][2];
-    if constexpr (KIND == Q2X_SEGMENT) {
+    static_assert(NV >= 2 && NV <= 4, "segments, triangles or tetrahedra");
+    if constexpr (NV == 2) {  // segment: length
       J = sqrt(ux * ux + uy * uy + uz * uz);
     } else {
       const double vx = xv[2][0] - xv[0][0], vy = xv[2][1] - xv[0][1], vz = xv[2][2] - xv[0][2];
       double crx, cry, crz;
       cross_nofma(ux, uy, uz, vx, vy, vz, crx, cry, crz);
-      if constexpr (KIND == Q2X_TET) {
+      if constexpr (NV == 4) {  // tetrahedron: |det|
         const double wx = xv[3][0] - xv[0][0], wy = xv[3][1] - xv[0][1], wz = xv[3][2] - xv[0][2];
         J = fabs(crx * wx + cry * wy + crz * wz);
       } else {
@@ -509,21 +530,30 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
     const double A1 = cp, A2 = h ? -sp : sp;
     const double B1 = im0 ? 0.0 : sq, B2 = im0 ? 0.0 : (h ? cq : -cq);
     const int idx = h ? (n * n + n - m) : (n * n + n + m);
-    double* const obase = ((o == 0) ? a.coeffs : a.coeffs2) + 2 * idx;
+    double* const obase = ((NOUT == 1 || o == 0) ? a.outs[0] : (o == 1 ? a.outs[1] : a.outs[2])) + 2 * idx;
     double* const pbase = a.partials + (tile * 2 * (int64_t)(NOUT * NCT) + g_coef) * 2;
     const int nsh = (n > shift) ? n - shift : 0;
     // segment state (uniform): first element, box id, scale exponents
     int seg = 0;
     int box = __builtin_amdgcn_readfirstlane(key);
-    int eb = 0, es0 = 0, es1 = 0;
+    int eb = 0;
+    int es[NOUT];
+#pragma unroll
+    for (int q = 0; q < NOUT; ++q) es[q] = 0;
     if constexpr (SCALED) {
       eb = __builtin_amdgcn_readfirstlane(seg_eb);
-      es0 = __builtin_amdgcn_readfirstlane(seg_es[0]);
-      es1 = __builtin_amdgcn_readfirstlane(seg_es[NOUT - 1]);
+#pragma unroll
+      for (int q = 0; q < NOUT; ++q) es[q] = __builtin_amdgcn_readfirstlane(seg_es[q]);
     }
+    // this lane's output's Es of the open segment
+    auto es_of = [&]() Q2X_INLINE -> int {
+      if constexpr (NOUT == 1) return es[0];
+      else if constexpr (NOUT == 2) return (o == 0) ? es[0] : es[1];
+      else return (o == 0) ? es[0] : ((o == 1) ? es[1] : es[2]);
+    };
     auto flush = [&](int sb, double t) Q2X_INLINE {
       if (box < 0 || box >= a.n_boxes) return;  // uniform
-      if constexpr (SCALED) t *= ldexp(invf, nsh * eb + ((o == 0) ? es0 : es1));
+      if constexpr (SCALED) t *= ldexp(invf, nsh * eb + es_of());
       // pair the halves: tr from lane c, ti from lane c + 32, on every lane
       const uint32_t lo = (uint32_t)__double2loint(t), hi = (uint32_t)__double2hiint(t);
       const auto slo = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
@@ -553,8 +583,8 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
       box = __builtin_amdgcn_readlane(key, i);
       if constexpr (SCALED) {
         eb = __builtin_amdgcn_readlane(seg_eb, i);
-        es0 = __builtin_amdgcn_readlane(seg_es[0], i);
-        es1 = __builtin_amdgcn_readlane(seg_es[NOUT - 1], i);
+#pragma unroll
+        for (int q = 0; q < NOUT; ++q) es[q] = __builtin_amdgcn_readlane(seg_es[q], i);
       }
     };
     const T* pv = stage + ((h ? CMAX : 0) + (act ? c : 0)) * SSTR;
@@ -603,12 +633,12 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
     __syncthreads();
     const int c = lane & 31;
     const int k = K0 + ((c < CJ) ? c : 0);
-    constexpr int OF = (NOUT == 1) ? 0 : ((UF % NOUT) == KI::slot(0) ? 0 : 1);
+    constexpr int OF = out_of_slot<KI>(UF % NOUT);
     int u = UF, ku = Plan::off(UF), sh = KI::shift(OF);
     double invf = inv_factorial(UF / NOUT + KI::depth(OF));
     static_for<UF, UL>([&](auto LL) Q2X_INLINE {
       constexpr int l = decltype(LL)::value;
-      constexpr int ol = (NOUT == 1) ? 0 : (((l + 1) % NOUT) == KI::slot(0) ? 0 : 1);
+      constexpr int ol = out_of_slot<KI>((l + 1) % NOUT);
       if (k >= Plan::off(l + 1)) {
         u = l + 1;
         ku = Plan::off(l + 1);
@@ -616,7 +646,7 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
         invf = inv_factorial((l + 1) / NOUT + KI::depth(ol));
       }
     });
-    const int o = (NOUT == 1) ? 0 : ((u % NOUT) == KI::slot(0) ? 0 : 1);
+    const int o = out_of_slot<KI>(u % NOUT);
     reduce_body(K0, CJ, u / NOUT, o, k - ku, sh, invf);
   };
   // unit and order of slot k (run-time decode; units are degree-major)
@@ -678,10 +708,11 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
   }
   constexpr bool HAS_DBL = KI::dbl(NOUT - 1);
   if constexpr (!HAS_DBL) {
-    // S holds degree N; emit the chain's last array
+    // S holds degree N; emit the chain's last array for every output (one
+    // weight per output)
     auto rec = [&](auto self, auto NNc, const CArr<T, P1>(&S)[NCH]) Q2X_INLINE -> void {
       constexpr int N = decltype(NNc)::value;
-      emit(IC<N>{}, IC<0>{}, S[NCH - 1]);
+      static_for<0, NOUT>([&](auto OO) Q2X_INLINE { emit(IC<N>{}, OO, S[NCH - 1]); });
       if constexpr (N < P) {
         if (N < p) {
           CArr<T, P1> nS[NCH];
@@ -741,7 +772,7 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
       int u, ku;
       const int k = K0 + (((lane & 31) < CJ) ? (lane & 31) : 0);
       decode(k, u, ku);
-      const int o = (NOUT == 1) ? 0 : ((u % NOUT) == KI::slot(0) ? 0 : 1);
+      const int o = out_of_slot<KI>(u % NOUT);
       __syncthreads();
       reduce_body(K0, CJ, u / NOUT, o, k - ku, KI::shift(o), inv_factorial(u / NOUT + KI::depth(o)));
     }

@@ -24,9 +24,9 @@ box coefficients written, B_occ (p+1)^2 16 B.
 """
 from __future__ import annotations
 
-TRI_SINGLE, TRI_DOUBLE, SEGMENT, TET, TRI_BOTH = 0, 1, 2, 3, 4
-NV = {TRI_SINGLE: 3, TRI_DOUBLE: 3, SEGMENT: 2, TET: 4, TRI_BOTH: 3}
-NOUT = {TRI_SINGLE: 1, TRI_DOUBLE: 1, SEGMENT: 1, TET: 1, TRI_BOTH: 2}
+TRI_SINGLE, TRI_DOUBLE, SEGMENT, TET, TRI_BOTH, SEGMENT_VEC = 0, 1, 2, 3, 4, 5
+NV = {TRI_SINGLE: 3, TRI_DOUBLE: 3, SEGMENT: 2, TET: 4, TRI_BOTH: 3, SEGMENT_VEC: 2}
+NOUT = {TRI_SINGLE: 1, TRI_DOUBLE: 1, SEGMENT: 1, TET: 1, TRI_BOTH: 2, SEGMENT_VEC: 3}
 GEOMETRY_FLOPS = 60
 
 
@@ -56,7 +56,7 @@ def recursion_flops(kind: int, p: int) -> int:
     if kind == TRI_SINGLE:
         for n in range(1, p + 1):
             f += ladder_flops(n, False) + 2 * ladder_flops(n, True)
-    elif kind == SEGMENT:
+    elif kind in (SEGMENT, SEGMENT_VEC):
         for n in range(1, p + 1):
             f += ladder_flops(n, False) + ladder_flops(n, True)
     elif kind == TET:
@@ -103,5 +103,6 @@ PEAK_HBM_GBS = 8000.0
 
 
 if __name__ == "__main__":
-    for k, name in ((0, "tri_single"), (1, "tri_double"), (2, "segment"), (3, "tet"), (4, "tri_both")):
+    for k, name in ((0, "tri_single"), (1, "tri_double"), (2, "segment"), (3, "tet"), (4, "tri_both"),
+                    (5, "segment_vec")):
         print(name, [recursion_flops(k, p) for p in (8, 12, 16, 20, 24)], [element_flops(k, p) for p in (8, 12, 16, 20, 24)])

@@ -14,18 +14,18 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libq2x.so")
 
-TRI_SINGLE, TRI_DOUBLE, SEGMENT, TET, TRI_BOTH = 0, 1, 2, 3, 4
-N_KINDS = 5
+TRI_SINGLE, TRI_DOUBLE, SEGMENT, TET, TRI_BOTH, SEGMENT_VEC = 0, 1, 2, 3, 4, 5
+N_KINDS = 6
 KIND_NAMES = {TRI_SINGLE: "tri_single", TRI_DOUBLE: "tri_double", SEGMENT: "segment", TET: "tet",
-              TRI_BOTH: "tri_both"}
-VERTS_PER_KIND = {TRI_SINGLE: 3, TRI_DOUBLE: 3, SEGMENT: 2, TET: 4, TRI_BOTH: 3}
+              TRI_BOTH: "tri_both", SEGMENT_VEC: "segment_vec"}
+VERTS_PER_KIND = {TRI_SINGLE: 3, TRI_DOUBLE: 3, SEGMENT: 2, TET: 4, TRI_BOTH: 3, SEGMENT_VEC: 2}
 FP64, FP32_MIXED = 0, 1
 NORM_FMM, NORM_MOMENT = 0, 1
 ACCUMULATE, PRESORTED = 1, 2
 P_MAX = 32
 FLAG_BAD_BOX, FLAG_NONFINITE, FLAG_RESERVED, FLAG_BAD_VERTEX, FLAG_NOT_SORTED = 1, 2, 4, 8, 16
 EXPORTS = ("q2x_workspace_bytes", "q2x_bucket_workspace_bytes", "q2x_bucket", "q2x_tri_single", "q2x_tri_double", "q2x_segment", "q2x_tet",
-           "q2x_tri_both", "q2x_status_get", "q2x_status_string", "q2x_profile_enable", "q2x_profile_reset",
+           "q2x_tri_both", "q2x_segment_vec", "q2x_status_get", "q2x_status_string", "q2x_profile_enable", "q2x_profile_reset",
            "q2x_profile_read", "q2x_version", "q2x_batch_plan", "q2x_batch_workspace_bytes", "q2x_batch_run", "q2x_batch_launch",
            "q2x_batch_job_status", "q2x_batch_groups", "q2x_batch_mode", "q2x_batch_destroy")
 
@@ -62,6 +62,8 @@ def lib():
             f.restype = ci
         L.q2x_tri_both.argtypes = [vp, i64, vp, i64, vp, vp, vp, vp, vp, i64, ci, ci, ci, cu, vp, vp, vp, sz, vp]
         L.q2x_tri_both.restype = ci
+        L.q2x_segment_vec.argtypes = [vp, i64, vp, i64, vp, vp, vp, vp, i64, ci, ci, ci, cu, vp, vp, sz, vp]
+        L.q2x_segment_vec.restype = ci
         L.q2x_bucket_workspace_bytes.argtypes = [i64, i64]
         L.q2x_bucket_workspace_bytes.restype = sz
         L.q2x_bucket.argtypes = [vp, i64, i64, vp, vp, vp, sz, vp]
@@ -147,8 +149,8 @@ def _out(out, nb, p, device, name="out"):
 def run(kind, verts, elems, density, elem_box, box_center, box_radius, p, precision=FP32_MIXED,
         norm=NORM_FMM, accumulate=False, presorted=False, out=None, workspace=None, stream=None):
     """Q2X for one mesh of one element kind; returns out [B, (p+1)^2, 2] float64."""
-    if kind == TRI_BOTH:
-        raise Q2XError("use tri_both() for the two-output kind")
+    if kind in (TRI_BOTH, SEGMENT_VEC):
+        raise Q2XError("use tri_both() / segment_vec() for the multi-output kinds")
     n_el = int(elems.shape[0]) if elems is not None else 0
     nb = int(box_center.shape[0])
     if elems is not None and elems.dim() == 2 and elems.shape[1] != VERTS_PER_KIND[kind]:
@@ -228,7 +230,12 @@ class BatchPlan:
             p = int(j["p"])
             nb = int(j["box_center"].shape[0])
             dev = j["verts"].device
-            out = _out(j.get("out"), nb, p, dev)
+            if kind == SEGMENT_VEC:  # density [N][3], out [3][B][(p+1)^2][2]
+                out = j.get("out")
+                if out is None:
+                    out = torch.empty((3, nb, (p + 1) ** 2, 2), dtype=torch.float64, device=dev)
+            else:
+                out = _out(j.get("out"), nb, p, dev)
             out2 = _out(j.get("out2"), nb, p, dev, "out2") if kind == TRI_BOTH else None
             self.outs.append((out, out2) if kind == TRI_BOTH else out)
             flags = (ACCUMULATE if j.get("accumulate") else 0) | (PRESORTED if j.get("presorted") else 0)
@@ -303,6 +310,33 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+def segment_vec(verts, segs, density3, elem_box, box_center, box_radius, p, precision=FP32_MIXED, norm=NORM_FMM,
+                accumulate=False, presorted=False, out=None, workspace=None, stream=None):
+    """Segments with a vector density [N][3]: coefficients [3][B][(p+1)^2][2], one per component."""
+    n_el = int(segs.shape[0]) if segs is not None else 0
+    nb = int(box_center.shape[0])
+    if segs is not None and segs.dim() == 2 and segs.shape[1] != 2:
+        raise Q2XError("segments need 2 vertices")
+    if density3 is not None and tuple(density3.shape) != (n_el, 3):
+        raise Q2XError(f"density3 must have shape {(n_el, 3)}")
+    shape = (3, nb, (p + 1) ** 2, 2)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float64, device=verts.device)
+    elif tuple(out.shape) != shape:
+        raise Q2XError(f"out must have shape {shape}")
+    if workspace is None:
+        workspace = alloc_workspace(SEGMENT_VEC, n_el, nb, p, precision, device=verts.device)
+    flags = (ACCUMULATE if accumulate else 0) | (PRESORTED if presorted else 0)
+    rc = lib().q2x_segment_vec(_ptr(verts, torch.float64, "verts"), int(verts.shape[0]),
+                               _ptr(segs, torch.int32, "segs"), n_el, _ptr(density3, torch.float64, "density3"),
+                               _ptr(elem_box, torch.int32, "elem_box"), _ptr(box_center, torch.float64, "box_center"),
+                               _ptr(box_radius, torch.float64, "box_radius"), nb, int(p), int(precision), int(norm),
+                               flags, _ptr(out, torch.float64, "out"), ctypes.c_void_p(workspace.data_ptr()),
+                               workspace.numel(), _stream(stream))
+    _check(rc)
+    return out
 
 
 def bucket(elem_box, n_boxes, stream=None, workspace=None):

@@ -1,0 +1,101 @@
+"""GPU parity of segments with a vector density (q2x_segment_vec): each
+component against the oracle's scalar-density segment integrals, bitwise
+against three q2x_segment calls, and inside a batch."""
+import numpy as np
+import pytest
+
+import metrics
+import oracle
+from gpu_util import FP32_MIXED, FP64, TOL, sample_boxes, small_job, sub_job
+
+pytestmark = pytest.mark.gpu
+
+
+def _c(a):
+    a = a.cpu().numpy()
+    return a[..., 0] + 1j * a[..., 1]
+
+
+def _run_vec(job, dens3, prec):
+    import torch
+    from paper_2107_10942_amd import q2x
+    v, e, d, eb, bc, br = q2x.job_tensors(job)
+    d3 = torch.as_tensor(dens3, dtype=torch.float64).contiguous().cuda()
+    ws = q2x.alloc_workspace(q2x.SEGMENT_VEC, job.n_elems, job.n_boxes, job.p, prec)
+    out = q2x.segment_vec(v, e, d3, eb, bc, br, job.p, precision=prec, workspace=ws)
+    st = q2x.status(ws)
+    torch.cuda.synchronize()
+    return [_c(out[c]) for c in range(3)], st
+
+
+def _run_scalar(job, dens, prec):
+    import torch
+    from paper_2107_10942_amd import q2x
+    v, e, d, eb, bc, br = q2x.job_tensors(job)
+    dd = torch.as_tensor(dens, dtype=torch.float64).contiguous().cuda()
+    o = q2x.segment(v, e, dd, eb, bc, br, job.p, precision=prec)
+    torch.cuda.synchronize()
+    return _c(o)
+
+
+def _check(F, job, dens, prec, boxes=None, label=""):
+    R = oracle.q2x(2, job.p, job.verts, job.elems, dens, job.elem_box, job.box_center, boxes=boxes)
+    en = oracle.element_norms(2, job.p, job.verts, job.elems, job.elem_box, job.box_center)
+    A = metrics.scale_denominator(en, dens, job.elem_box, job.n_boxes, boxes)
+    err = metrics.scale_aware_error(F, R, A, job.p)
+    worst = float(np.max(err)) if err.size else 0.0
+    print(label, f"{worst:.3e}", flush=True)
+    assert worst <= TOL[prec], (label, worst)
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32_MIXED])
+@pytest.mark.parametrize("p", [0, 3, 8, 12, 17, 24, 32])
+def test_segment_vec_parity_and_bitwise(prec, p):
+    job = small_job(2, 611, 30, p, seed=700 + p)
+    dens3 = np.random.default_rng(p).uniform(-1, 1, (job.n_elems, 3))
+    dens3[::17, 1] = 0.0  # zero components in some elements
+    F, st = _run_vec(job, dens3, prec)
+    assert st == (0, 0, 0)
+    for c in range(3):
+        _check(F[c], job, dens3[:, c].copy(), prec, label=f"segvec p={p} prec={prec} c={c}")
+        assert np.array_equal(F[c], _run_scalar(job, dens3[:, c].copy(), prec))
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32_MIXED])
+def test_segment_vec_random_walks_sampled(prec):
+    """1,000,000 random-walk segments (level 6, p = 12) with a vector density
+    (the walk tangent times a U[-1,1] strength, as in vortex filaments)."""
+    from q2x_inputs import configs
+    job = configs.random_filaments()
+    rng = np.random.default_rng(5)
+    t = job.verts[job.elems[:, 1]] - job.verts[job.elems[:, 0]]
+    t /= np.linalg.norm(t, axis=1, keepdims=True)
+    dens3 = t * rng.uniform(-1, 1, (job.n_elems, 1))
+    F, st = _run_vec(job, dens3, prec)
+    assert st == (0, 0, 0)
+    boxes = sample_boxes(job, 12, seed=6)
+    keep = np.isin(job.elem_box, boxes)
+    sj = sub_job(job, boxes)
+    for c in range(3):
+        _check(F[c][boxes], sj, dens3[keep, c].copy(), prec, boxes=boxes, label=f"walks c={c} prec={prec}")
+
+
+def test_segment_vec_in_a_batch():
+    import torch
+    from paper_2107_10942_amd import q2x
+    jobs, ref = [], []
+    for i, (p, prec) in enumerate([(9, FP32_MIXED), (16, FP64), (12, FP32_MIXED)]):
+        job = small_job(2, 300 + 100 * i, 12, p, seed=40 + i)
+        dens3 = np.random.default_rng(i).uniform(-1, 1, (job.n_elems, 3))
+        v, e, d, eb, bc, br = q2x.job_tensors(job)
+        jobs.append(dict(kind=q2x.SEGMENT_VEC, verts=v, elems=e,
+                         density=torch.as_tensor(dens3, dtype=torch.float64).contiguous().cuda(), elem_box=eb,
+                         box_center=bc, p=p, precision=prec))
+        ref.append(_run_vec(job, dens3, prec)[0])
+    plan = q2x.BatchPlan(jobs)
+    outs = plan.run()
+    torch.cuda.synchronize()
+    for i, o in enumerate(outs):
+        for c in range(3):
+            assert np.array_equal(_c(o[c]), ref[i][c]), (i, c)
+    plan.close()
