@@ -44,6 +44,7 @@ def lib():
         L.orc_q2x_boxes.argtypes = [ci, ci, ci, dp, i64, ip, i64, dp, ip, dp, i64, lp, i64, ci, ci, dp]
         L.orc_q2x.argtypes = [ci, ci, ci, dp, i64, ip, i64, dp, ip, dp, i64, ci, ci, dp]
         L.orc_element_norms.argtypes = [ci, ci, dp, i64, ip, i64, ip, dp, i64, ci, ci, dp]
+        L.orc_eval.argtypes = [ci, ci, dp, i64, ip, i64, ip, dp, i64, dp, ci, ci, dp, dp]
         L.orc_max_threads.argtypes = []
         _lib = L
     return _lib
@@ -152,6 +153,28 @@ def q2x(kind, p, verts, elems, density, elem_box, box_center, norm=NORM_FMM, box
                                  threads, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     assert rc == 0, rc
     return _cplx(out)
+
+
+def evaluate(kind, p, verts, elems, elem_box, box_center, local, nodes=0, threads=0):
+    """Receiving side: per element, sum_{n,m} L_b[n,m] int_e R_n^m(y - c_b) (double layer: n.grad R).
+    `local` is complex [n_boxes][(p+1)^2].  Returns (values complex [N], scale [N])."""
+    verts, pv = _d(verts)
+    elems, pe = _i(elems)
+    elem_box, peb = _i(elem_box)
+    box_center, pbc = _d(box_center)
+    nv = verts.reshape(-1, 3).shape[0]
+    ne = elem_box.shape[0]
+    nb = box_center.reshape(-1, 3).shape[0]
+    assert elems.size == ne * VERTS_PER_KIND[kind]
+    loc = np.ascontiguousarray(np.stack([np.real(local), np.imag(local)], axis=-1), dtype=np.float64)
+    assert loc.shape == (nb, (p + 1) ** 2, 2)
+    out = np.zeros((ne, 2))
+    sc = np.zeros(ne)
+    dp = ctypes.POINTER(ctypes.c_double)
+    rc = lib().orc_eval(kind, p, pv, nv, pe, ne, peb, pbc, nb, loc.ctypes.data_as(dp), nodes, threads,
+                        out.ctypes.data_as(dp), sc.ctypes.data_as(dp))
+    assert rc == 0, rc
+    return out[:, 0] + 1j * out[:, 1], sc
 
 
 def element_norms(kind, p, verts, elems, elem_box, box_center, nodes=0, threads=0):

@@ -524,6 +524,59 @@ int orc_element_norms(int kind, int p, const double *verts, int64_t nv, const in
   return err;
 }
 
+/*
+ * Receiving side (Sec. 2 after Eq. (5): the same integrals serve the
+ * evaluation stage of a Galerkin method): for every element e with box b,
+ *   out[e]   = sum_{n<=p} sum_{m=-n..n} L_b[n,m] * I_e[n,m]
+ *   scale[e] = sum_{n,m} |L_b[n,m]| |I_e[n,m]|
+ * with I_e the unit-density integrals of orc_element_integral (int R_n^m, or
+ * n.grad R_n^m for the double layer) about the box centre, L [nb][(p+1)^2][2]
+ * local coefficients of a field sum L_n^m R_n^m(y - c_b).  Elements with a
+ * box id outside [0, nb) get 0.  OpenMP over elements.
+ */
+int orc_eval(int kind, int p, const double *verts, int64_t nv, const int32_t *elems, int64_t ne,
+             const int32_t *elem_box, const double *box_center, int64_t nb, const double *local, int nodes,
+             int nthreads, double *out, double *scale) {
+  if (p < 0 || p > ORC_PMAX || kind < 0 || kind > 3) return -1;
+  const int nvk = nverts_of(kind);
+  const int ncoef = (p + 1) * (p + 1);
+  int err = 0;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+  for (int64_t e = 0; e < ne; ++e) {
+    out[2 * e] = out[2 * e + 1] = 0.0;
+    if (scale) scale[e] = 0.0;
+    const int32_t b = elem_box[e];
+    if (b < 0 || b >= nb) continue;
+    double xv[12];
+    int ok = 1;
+    for (int k = 0; ok && k < nvk; ++k) {
+      const int32_t vi = elems[(int64_t)e * nvk + k];
+      if (vi < 0 || vi >= nv) { ok = 0; break; }
+      xv[3 * k] = verts[3 * (int64_t)vi];
+      xv[3 * k + 1] = verts[3 * (int64_t)vi + 1];
+      xv[3 * k + 2] = verts[3 * (int64_t)vi + 2];
+    }
+    if (!ok) { err = -3; continue; }
+    double *I = (double *)malloc(sizeof(double) * 2 * (size_t)ncoef);
+    orc_element_integral(kind, p, xv, &box_center[3 * (int64_t)b], nodes, I, NULL);
+    const double *L = &local[2 * (size_t)ncoef * (size_t)b];
+    double re = 0.0, im = 0.0, sc = 0.0;
+    for (int o = 0; o < ncoef; ++o) {
+      re += L[2 * o] * I[2 * o] - L[2 * o + 1] * I[2 * o + 1];
+      im += L[2 * o] * I[2 * o + 1] + L[2 * o + 1] * I[2 * o];
+      sc += hypot(L[2 * o], L[2 * o + 1]) * hypot(I[2 * o], I[2 * o + 1]);
+    }
+    out[2 * e] = re;
+    out[2 * e + 1] = im;
+    if (scale) scale[e] = sc;
+    free(I);
+  }
+  return err;
+}
+
 int orc_max_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

@@ -477,3 +477,89 @@ def test_box_sum_is_sum_of_elements():
     for e in members:
         tot = tot + _one_element_q2x(job.kind, job.verts[job.elems[e]], job.density[e], job.box_center[b], job.p)
     np.testing.assert_allclose(F[b], tot, atol=1e-16)
+
+
+# ------------------------------------------------- receiving side (evaluation)
+def _eval_one(kind, xv, c, local, p):
+    nv = xv.shape[0]
+    vals, sc = oracle.evaluate(kind, p, xv, np.arange(nv, dtype=np.int32)[None], np.zeros(1, np.int32),
+                               np.asarray(c, dtype=float)[None], local[None])
+    return vals[0], sc[0]
+
+
+@pytest.mark.parametrize("kind", ["single", "double", "segment", "tet"])
+def test_eval_low_order_closed_forms(kind):
+    """A field 1 (L_0^0 = 1) integrates to the element's measure (0 for the
+    double layer: grad 1 = 0); R_1^0 = -z and R_1^{-1} = (y + i x)/2 (the
+    normalisation of Sec. 3.2, Eq. (10)) give -measure * (centroid height) and
+    measure * (y_c + i x_c)/2 (double layer: the normal's components times the
+    area)."""
+    nv = {"single": 3, "double": 3, "segment": 2, "tet": 4}[kind]
+    code = {"single": 0, "double": 1, "segment": 2, "tet": 3}[kind]
+    xv = _rand_simplex(nv)
+    c = np.array([0.05, 0.02, -0.03])
+    p = 3
+    if kind == "segment":
+        mu = np.linalg.norm(xv[1] - xv[0])
+    elif kind in ("single", "double"):
+        mu = 0.5 * np.linalg.norm(np.cross(xv[1] - xv[0], xv[2] - xv[0]))
+    else:
+        mu = abs(np.dot(np.cross(xv[1] - xv[0], xv[2] - xv[0]), xv[3] - xv[0])) / 6
+    xc, yc, zc = xv.mean(axis=0) - c
+    L = np.zeros((p + 1) ** 2, complex)
+    L[idx(0, 0)] = 1.0
+    v, _ = _eval_one(code, xv, c, L, p)
+    assert abs(v - (0.0 if kind == "double" else mu)) < 1e-15 * max(mu, 1)
+    L[:] = 0
+    L[idx(1, 0)] = 2.5
+    v, _ = _eval_one(code, xv, c, L, p)
+    if kind == "double":
+        cr = np.cross(xv[1] - xv[0], xv[2] - xv[0])
+        nz = cr[2] / np.linalg.norm(cr)
+        assert abs(v + 2.5 * mu * nz) < 1e-15
+    else:
+        assert abs(v + 2.5 * mu * zc) < 1e-15
+    L[:] = 0
+    L[idx(1, -1)] = 1.0 - 0.5j
+    v, _ = _eval_one(code, xv, c, L, p)
+    if kind == "double":
+        cr = np.cross(xv[1] - xv[0], xv[2] - xv[0])
+        nx, ny, _ = cr / np.linalg.norm(cr)
+        assert abs(v - (1.0 - 0.5j) * mu * (ny + 1j * nx) / 2) < 1e-15
+    else:
+        assert abs(v - (1.0 - 0.5j) * mu * (yc + 1j * xc) / 2) < 1e-15
+
+
+@pytest.mark.parametrize("kind", ["single", "double", "segment", "tet"])
+def test_eval_point_source_local_expansion(kind):
+    """The local expansion about c of G(s, y) = 1/(4 pi |y - s|), built from an
+    independent S_n^m (scipy) by the addition theorem of Sec. 3.2, Eq. (13):
+    L_n^m = (1/4pi)(-1)^n S_n^{-m}(s - c).  Its integral over an element near c
+    must match direct quadrature of G (of dG/dn for the double layer) within
+    the rigorous truncation bound."""
+    nv = {"single": 3, "double": 3, "segment": 2, "tet": 4}[kind]
+    code = {"single": 0, "double": 1, "segment": 2, "tet": 3}[kind]
+    xv = _rand_simplex(nv, scale=0.25, centre=(0.05, 0.0, 0.02))
+    c = np.array([0.02, -0.01, 0.03])
+    s_pt = np.array([1.1, -0.7, 0.9])
+    a = float(np.max(np.linalg.norm(xv - c, axis=1)))
+    d = float(np.linalg.norm(s_pt - c))
+    if kind == "segment":
+        mu = np.linalg.norm(xv[1] - xv[0])
+    elif kind in ("single", "double"):
+        mu = 0.5 * np.linalg.norm(np.cross(xv[1] - xv[0], xv[2] - xv[0]))
+    else:
+        mu = abs(np.dot(np.cross(xv[1] - xv[0], xv[2] - xv[0]), xv[3] - xv[0])) / 6
+    ref = refmath.direct_potential({"single": "single", "double": "double", "segment": "segment",
+                                    "tet": "tet"}[kind], s_pt, list(xv), k=40)
+    # (for the double layer direct_potential gives n.(s - y)/(4 pi |s - y|^3) = dG/dn_y)
+    for p in (6, 12, 20):
+        S = refmath.solid_S_scipy(p, *(s_pt - c))
+        L = np.zeros((p + 1) ** 2, complex)
+        for n in range(p + 1):
+            for m in range(-n, n + 1):
+                L[idx(n, m)] = (-1) ** n * S[idx(n, -m)] / (4 * math.pi)
+        v, sc = _eval_one(code, xv, c, L, p)
+        bound = refmath.truncation_bound("double" if kind == "double" else "single", p, mu, a, d)
+        assert abs(v.imag) < 1e-14 * sc
+        assert abs(v.real - ref) <= bound + 1e-14 * abs(ref) + 1e-15, (kind, p, v, ref, bound)
