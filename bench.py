@@ -237,6 +237,50 @@ def coef_complex(t):
     return a[..., 0] + 1j * a[..., 1]
 
 
+def receiving_side(dev, reps=20):
+    """q2x_eval on the headline sphere at p = 16: the local expansion of each
+    box integrated over its triangles (single and double layer), FP32-mixed and
+    FP64.  Local coefficients: seeded U[-1,1]^2 times (1/h)^n, h the leaf box
+    size.  Timed with HIP events on the stream the calls are enqueued on."""
+    import numpy as np
+    import torch
+
+    from paper_2107_10942_amd import flops, q2x
+    from q2x_inputs import configs
+    single, double = configs.perturbed_sphere_pair()
+    p, N, B = single.p, single.n_elems, single.n_boxes
+    rng = np.random.default_rng(12)
+    nidx = np.floor(np.sqrt(np.arange((p + 1) ** 2))).astype(int)
+    scale = (1.0 / single.boxes.h) ** nidx
+    L = np.stack([rng.uniform(-1, 1, (B, (p + 1) ** 2)) * scale, rng.uniform(-1, 1, (B, (p + 1) ** 2)) * scale], -1)
+    lt = torch.as_tensor(L, dtype=torch.float64, device=dev).contiguous()
+    v, e, d, eb, bc, br = q2x.job_tensors(single, dev)
+    out = torch.empty((N, 2), dtype=torch.float64, device=dev)
+    ws = q2x.alloc_eval_workspace(N, B, device=dev)
+    occ = int(np.unique(single.elem_box).size)
+    res = {"workload": f"perturbed icosphere k=6, {N} triangles, {B} boxes, p={p}", "elements": N, "p": p}
+    stream = torch.cuda.current_stream()
+    for kind, kname in ((q2x.TRI_SINGLE, "tri_single"), (q2x.TRI_DOUBLE, "tri_double")):
+        for prec, pn in ((q2x.FP32_MIXED, "fp32_mixed"), (q2x.FP64, "fp64")):
+            for _ in range(3):
+                q2x.evaluate(kind, v, e, eb, bc, lt, p, precision=prec, out=out, workspace=ws, stream=stream)
+            torch.cuda.synchronize()
+            a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                q2x.evaluate(kind, v, e, eb, bc, lt, p, precision=prec, out=out, workspace=ws, stream=stream)
+            z.record(stream)
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(z) / reps
+            fl = flops.eval_element_flops(kind, p) * N
+            res[f"{kname}_{pn}"] = {"call_ms": ms, "elements_per_s": N / (ms * 1e-3),
+                                    "terms_per_s": N * (p + 1) ** 2 / (ms * 1e-3),
+                                    "call_tflops": fl / (ms * 1e-3) / 1e12,
+                                    "algorithmic_bytes": flops.eval_launch_bytes(kind, p, N, occ),
+                                    "status_flags": q2x.status(ws)[0]}
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -391,6 +435,7 @@ def main():
 
     if not args.no_configs:
         line["other_workloads"] = other_workloads(dev)
+        line["receiving_side"] = receiving_side(dev)
     if not args.no_batch:
         line["batch_workload"] = batch_workload(dev)
     if not args.no_serving:

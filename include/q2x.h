@@ -201,6 +201,40 @@ q2x_status q2x_bucket(const int32_t* elem_box, int64_t n_elems, int64_t n_boxes,
                       void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * Receiving side: integrals of local expansions over elements, the evaluation
+ * stage of a Galerkin method, which uses the same element integrals as Q2X
+ * (Sec. 2 after Eq. (5); the recursions of Sec. 3.4, Eqs. (50)-(56)).
+ *   kind       Q2X_TRI_SINGLE (int_e R_n^m dS), Q2X_TRI_DOUBLE
+ *              (int_e n . grad_y R_n^m dS, n the unit normal (x2-x1) x (x3-x1)),
+ *              Q2X_SEGMENT (int_e R_n^m ds) or Q2X_TET (int_e R_n^m dV)
+ *   elems      [n_elems][2|3|4] int32 vertex indices, as for the Q2X calls
+ *   elem_box   [n_elems] int32 box of each element; box_center [n_boxes][3]
+ *   local      [n_boxes][(p+1)^2][2] doubles: coefficients L_n^m of the field
+ *              sum_{n<=p} sum_m L_n^m R_n^m(y - c_b) in box b, (n, m) at
+ *              index n*n + n + m (the layout of coeffs above)
+ *   out        [n_elems][2] doubles, out: for element e of box b,
+ *              out[e] = sum_{n<=p} sum_m L_b[n,m] int_e R_n^m(y - c_b)
+ *              (with Q2X_ACCUMULATE the value is added to out[e])
+ *   flags      Q2X_ACCUMULATE; Q2X_PRESORTED (elem_box non-decreasing: skip
+ *              the grouping of elements by box, which only orders the work so
+ *              that neighbouring lanes share rows of `local`; results do not
+ *              depend on it)
+ *   precision  Q2X_FP64, or Q2X_FP32_MIXED (recursion in FP32 on (y - c)/a_e;
+ *              weights a_e^n/(n+k)!, products with L and sums in FP64)
+ * Elements with a box id outside [0, n_boxes), bad vertex indices or
+ * non-finite coordinates get 0 (nothing added when accumulating), set the
+ * matching Q2X_FLAG_* and are counted as skipped; degenerate elements get 0
+ * and are counted.  Non-finite entries of `local` reach the outputs of the
+ * elements of that box.  Workspace: q2x_eval_workspace_bytes(n_elems,
+ * n_boxes) bytes; status as for the other calls.
+ */
+size_t q2x_eval_workspace_bytes(int64_t n_elems, int64_t n_boxes);
+q2x_status q2x_eval(int kind, const double* verts, int64_t n_verts, const int32_t* elems, int64_t n_elems,
+                    const int32_t* elem_box, const double* box_center, int64_t n_boxes, const double* local, int p,
+                    int precision, unsigned flags, double* out, void* workspace, size_t workspace_bytes,
+                    void* stream);
+
+/*
  * Batches: many meshes (jobs) in one replayed launch sequence.  A job is one
  * single call's arguments; kind may be any q2x_kind (density2/coeffs2 only for
  * Q2X_TRI_BOTH; for Q2X_SEGMENT_VEC density is [N][3] and coeffs [3][B][..]).  Q2X_PRESORTED is accepted and has no effect (the batch always

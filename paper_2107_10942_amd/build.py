@@ -1,8 +1,9 @@
 """Build the gfx950 Q2X library (``libq2x.so``) in-tree with hipcc.
 
 Every HIP source is compiled for gfx950 only.  The twelve tile-kernel
-instantiation units (6 element kinds x 2 precisions) are large, fully
-unrolled translation units, so they compile in parallel.
+instantiation units (6 element kinds x 2 precisions) and the eight
+receiving-side units (4 kinds x 2 precisions) are large, fully unrolled
+translation units, so they compile in parallel.
 """
 from __future__ import annotations
 
@@ -24,6 +25,7 @@ COMMON = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",
 
 SIMPLE = ["q2x_api.hip", "q2x_bucket.hip", "q2x_dispatch.hip", "q2x_batch.hip"]
 INST = [(k, f) for k in range(6) for f in (0, 1)]
+EVAL_INST = [(k, f) for k in range(4) for f in (0, 1)]
 
 
 def _units():
@@ -34,6 +36,10 @@ def _units():
     for k, f in INST:
         obj = os.path.join(BUILD, f"q2x_inst_k{k}_f{f}.o")
         units.append((obj, [os.path.join(CSRC, "q2x_inst.hip")], [f"-DQ2X_INST_KIND={k}", f"-DQ2X_INST_F32={f}"]))
+    for k, f in EVAL_INST:
+        obj = os.path.join(BUILD, f"q2x_eval_k{k}_f{f}.o")
+        units.append((obj, [os.path.join(CSRC, "q2x_eval_inst.hip")],
+                      [f"-DQ2X_INST_KIND={k}", f"-DQ2X_INST_F32={f}"]))
     return units
 
 
@@ -42,7 +48,7 @@ def source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
     for f in ("q2x_tile.hpp", "q2x_internal.hpp", "q2x_api.hip", "q2x_bucket.hip", "q2x_dispatch.hip", "q2x_inst.hip",
-              "q2x_batch.hip"):
+              "q2x_batch.hip", "q2x_eval.hpp", "q2x_eval_inst.hip"):
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -80,7 +86,7 @@ def build(force: bool = True, verbose: bool = False, jobs: int | None = None) ->
     jobs = jobs or min(8, os.cpu_count() or 4)
     if todo:
         # largest units first
-        todo.sort(key=lambda u: 0 if "inst" in u[0] else 1)
+        todo.sort(key=lambda u: 0 if "inst" in u[0] else (1 if "eval" in u[0] else 2))
         with ThreadPoolExecutor(max_workers=jobs) as ex:
             list(ex.map(lambda u: _compile(u, verbose), todo))
     objs = [u[0] for u in units]

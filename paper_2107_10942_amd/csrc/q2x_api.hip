@@ -262,6 +262,64 @@ q2x_status q2x_segment_vec(const double* verts, int64_t n_verts, const int32_t* 
              precision, norm, flags, outs, workspace, workspace_bytes, stream);
 }
 
+size_t q2x_eval_workspace_bytes(int64_t n_elems, int64_t n_boxes) {
+  if (n_elems < 0 || n_boxes < 0) return 0;
+  return align_up(sizeof(Status)) + align_up(bucket_scratch_bytes(n_elems, n_boxes));
+}
+
+q2x_status q2x_eval(int kind, const double* verts, int64_t n_verts, const int32_t* elems, int64_t n_elems,
+                    const int32_t* elem_box, const double* box_center, int64_t n_boxes, const double* local, int p,
+                    int precision, unsigned flags, double* out, void* workspace, size_t workspace_bytes,
+                    void* stream) {
+  if (kind < Q2X_TRI_SINGLE || kind > Q2X_TET) return Q2X_ERR_ARG;
+  if (p < 0 || p > Q2X_P_MAX) return Q2X_ERR_P_RANGE;
+  if (n_verts < 0 || n_elems < 0 || n_boxes < 0 || n_elems >= ((int64_t)1 << 31) - 64 ||
+      n_boxes >= ((int64_t)1 << 31) - 1 || n_verts >= ((int64_t)1 << 31))
+    return Q2X_ERR_ARG;
+  if (precision != Q2X_FP64 && precision != Q2X_FP32_MIXED) return Q2X_ERR_ARG;
+  if (flags & ~(unsigned)(Q2X_ACCUMULATE | Q2X_PRESORTED)) return Q2X_ERR_ARG;
+  if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return Q2X_ERR_WORKSPACE;
+  if (n_boxes > 0 && (!box_center || !local)) return Q2X_ERR_ARG;
+  if (n_elems > 0 && (!verts || !elems || !elem_box || !out)) return Q2X_ERR_ARG;
+  if (((uintptr_t)verts % 8) || ((uintptr_t)box_center % 8) || ((uintptr_t)local % 8) || ((uintptr_t)out % 8) ||
+      ((uintptr_t)elems % 4) || ((uintptr_t)elem_box % 4))
+    return Q2X_ERR_ARG;
+  const int P = bucket_order(p);
+  if (P < 0) return Q2X_ERR_UNSUPPORTED;
+  if (workspace_bytes < q2x_eval_workspace_bytes(n_elems, n_boxes)) return Q2X_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  Status* st = (Status*)workspace;
+  int32_t* scratch = (int32_t*)((char*)workspace + align_up(sizeof(Status)));
+  const bool presorted = (flags & Q2X_PRESORTED) != 0;
+  const int32_t* keys = elem_box;
+  const int32_t* perm = nullptr;
+  hipError_t err;
+  // grouping by box only orders the work (lanes of a wavefront then share
+  // rows of L); each element's result does not depend on it
+  if (presorted || n_elems == 0) err = clear_status(st, s);
+  else err = bucket_elements(elem_box, n_elems, n_boxes, scratch, st, s, &keys, &perm);
+  if (err != hipSuccess) return Q2X_ERR_HIP;
+  if (n_elems == 0) return Q2X_OK;
+  EvalArgs a{};
+  a.verts = verts;
+  a.elems = elems;
+  a.keys = keys;
+  a.perm = perm;
+  a.box_center = box_center;
+  a.local = local;
+  a.out = out;
+  a.status = st;
+  a.n_verts = n_verts;
+  a.n_pos = n_elems;
+  a.n_boxes = n_boxes;
+  a.p = p;
+  a.accumulate = (flags & Q2X_ACCUMULATE) ? 1 : 0;
+  a.count_bad_ids = presorted ? 1 : 0;
+  const int64_t n_tiles = (n_elems + kTile - 1) / kTile;
+  if (launch_eval(kind, precision, P, a, n_tiles, s) != hipSuccess) return Q2X_ERR_HIP;
+  return Q2X_OK;
+}
+
 size_t q2x_bucket_workspace_bytes(int64_t n_elems, int64_t n_boxes) {
   if (n_elems < 0 || n_boxes < 0) return 0;
   return align_up(sizeof(Status)) + align_up(bucket_scratch_bytes(n_elems, n_boxes));

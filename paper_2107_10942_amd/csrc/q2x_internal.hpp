@@ -75,6 +75,25 @@ struct BatchJob {
   int32_t kind, prec, P, p, norm, accumulate, nout, group, dstride;
 };
 
+// Arguments of the receiving-side kernel (integrals of local expansions over
+// elements; one lane per element, no reduction).
+struct EvalArgs {
+  const double* verts;
+  const int32_t* elems;
+  const int32_t* keys;   // box id per position (sorted, or elem_box itself)
+  const int32_t* perm;   // position -> element (nullptr: identity)
+  const double* box_center;
+  const double* local;   // [n_boxes][(p+1)^2][2]
+  double* out;           // [n_elems][2]
+  Status* status;
+  int64_t n_verts;
+  int64_t n_pos;
+  int64_t n_boxes;
+  int p;
+  int accumulate;
+  int count_bad_ids;     // presorted input (no bucketing pass): count ids outside [0, n_boxes) here
+};
+
 // Arguments of the fix-up kernel (boxes cut by tile edges, empty boxes).
 struct FixupArgs {
   const int32_t* box_start;  // written by the tile kernel (unused when n_pos == 0)
@@ -197,4 +216,5 @@ __device__ __forceinline__ void fixup_box(int lane, int64_t s, int64_t t, int64_
 namespace q2x {
 hipError_t launch_tiles(int kind, int prec, int P, const TileArgs& a, int64_t n_tiles, hipStream_t s);
 int bucket_order(int p);  // smallest compiled bucket >= p (or -1)
+hipError_t launch_eval(int kind, int prec, int P, const EvalArgs& a, int64_t n_tiles, hipStream_t s);
 }  // namespace q2x

@@ -234,6 +234,120 @@ __host__ __device__ constexpr double inv_factorial(int k) {
 }
 constexpr int kNoExp = -4000;  // exponent of a box segment with no nonzero weight
 
+// Per-element data of the recursion: validity and status bits, Jacobian J
+// (Sec. 3.1, Eq. (9)), unit normal (triangles), the element scale a_e
+// (largest vertex distance from the box centre; 1 when unscaled) and the
+// vertex coordinates relative to the box centre divided by a_e, in the forms
+// the ladder takes ((x, y)/2, z, (x, y)).
+template <int NV, typename T>
+struct ElemGeom {
+  bool ok;
+  uint32_t flag;
+  double J, nx, ny, nz, scl;
+  T vxr[NV], vxi[NV], vz[NV], vxr2[NV], vxi2[NV];
+};
+
+// Element e of box `key` (box_ok: key names a box); sigma[0..nsig) are its
+// densities, checked for finiteness with the coordinates.  A bad vertex index
+// or a non-finite input clears ok and sets the matching status bit; the
+// element then has J = 0 and zero coordinates.
+template <int NV, typename T, bool SCALED>
+__device__ __forceinline__ ElemGeom<NV, T> element_geometry(const double* verts, int64_t n_verts,
+                                                            const int32_t* elems, int64_t e,
+                                                            const double* box_center, int key, bool box_ok,
+                                                            const double* sigma, int nsig) {
+  ElemGeom<NV, T> g;
+  g.flag = 0;
+  bool ok = box_ok;
+  double xv[NV][3];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) xv[k][0] = xv[k][1] = xv[k][2] = 0.0;
+  double cx = 0.0, cy = 0.0, cz = 0.0;
+  if (ok) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const int32_t vi = elems[e * NV + k];
+      if (vi < 0 || vi >= n_verts) {
+        ok = false;
+        g.flag |= Q2X_FLAG_BAD_VERTEX;
+      } else {
+        xv[k][0] = verts[3 * (int64_t)vi];
+        xv[k][1] = verts[3 * (int64_t)vi + 1];
+        xv[k][2] = verts[3 * (int64_t)vi + 2];
+      }
+    }
+    cx = box_center[3 * (int64_t)key];
+    cy = box_center[3 * (int64_t)key + 1];
+    cz = box_center[3 * (int64_t)key + 2];
+  }
+  if (ok) {
+    bool fin = isfinite(cx) && isfinite(cy) && isfinite(cz);
+    for (int o = 0; o < nsig; ++o) fin = fin && isfinite(sigma[o]);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) fin = fin && isfinite(xv[k][0]) && isfinite(xv[k][1]) && isfinite(xv[k][2]);
+    if (!fin) {
+      ok = false;
+      g.flag |= Q2X_FLAG_NONFINITE;
+    }
+  }
+  // Jacobian (Eq. (9)) and unit normal from the absolute vertices
+  double J = 0.0, nx = 0.0, ny = 0.0, nz = 0.0;
+  if (ok) {
+    const double ux = xv[1][0] - xv[0][0], uy = xv[1][1] - xv[0][1], uz = xv[1][2] - xv[0][2];
+    static_assert(NV >= 2 && NV <= 4, "segments, triangles or tetrahedra");
+    if constexpr (NV == 2) {  // segment: length
+      J = sqrt(ux * ux + uy * uy + uz * uz);
+    } else {
+      const double vx = xv[2][0] - xv[0][0], vy = xv[2][1] - xv[0][1], vz = xv[2][2] - xv[0][2];
+      double crx, cry, crz;
+      cross_nofma(ux, uy, uz, vx, vy, vz, crx, cry, crz);
+      if constexpr (NV == 4) {  // tetrahedron: |det|
+        const double wx = xv[3][0] - xv[0][0], wy = xv[3][1] - xv[0][1], wz = xv[3][2] - xv[0][2];
+        J = fabs(crx * wx + cry * wy + crz * wz);
+      } else {
+        J = sqrt(crx * crx + cry * cry + crz * crz);
+        if (J > 0.0) {
+          nx = crx / J;
+          ny = cry / J;
+          nz = crz / J;
+        }
+      }
+    }
+  }
+
+  // element scale a_e (FP32 path) and the recursion's vertex data
+  double X[NV][3];
+  double amax2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    X[k][0] = ok ? xv[k][0] - cx : 0.0;
+    X[k][1] = ok ? xv[k][1] - cy : 0.0;
+    X[k][2] = ok ? xv[k][2] - cz : 0.0;
+    amax2 = fmax(amax2, X[k][0] * X[k][0] + X[k][1] * X[k][1] + X[k][2] * X[k][2]);
+  }
+  double scl = 1.0;
+  if constexpr (SCALED) {
+    scl = sqrt(amax2);
+    if (!(scl > 0.0)) scl = 1.0;
+  }
+  const double inv_scl = 1.0 / scl;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    g.vxr[k] = (T)(0.5 * X[k][0] * inv_scl);
+    g.vxi[k] = (T)(0.5 * X[k][1] * inv_scl);
+    g.vz[k] = (T)(X[k][2] * inv_scl);
+    g.vxr2[k] = (T)(X[k][0] * inv_scl);
+    g.vxi2[k] = (T)(X[k][1] * inv_scl);
+  }
+  g.ok = ok;
+  g.J = J;
+  g.nx = nx;
+  g.ny = ny;
+  g.nz = nz;
+  g.scl = scl;
+  return g;
+}
+
 template <int P, int KIND, typename T>
 __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t n_tiles) {
   using KI = KindInfo<KIND>;
@@ -304,96 +418,20 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
   const int key = in_range ? (int)(a.keys[q] - key_off) : INT32_MIN;
   const bool box_ok = in_range && key >= 0 && key < a.n_boxes;  // (bad ids were counted by the bucketing)
   const int64_t e = in_range ? (a.perm ? (int64_t)a.perm[q] - elem_off : q) : 0;
-  uint32_t flag = 0;
-  bool ok = box_ok;
-  double xv[NV][3];
-#pragma unroll
-  for (int k = 0; k < NV; ++k) xv[k][0] = xv[k][1] = xv[k][2] = 0.0;
   double sigma[NOUT];
 #pragma unroll
-  for (int o = 0; o < NOUT; ++o) sigma[o] = 0.0;
-  double cx = 0.0, cy = 0.0, cz = 0.0;
-  if (ok) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      const int32_t vi = a.elems[e * NV + k];
-      if (vi < 0 || vi >= a.n_verts) {
-        ok = false;
-        flag |= Q2X_FLAG_BAD_VERTEX;
-      } else {
-        xv[k][0] = a.verts[3 * (int64_t)vi];
-        xv[k][1] = a.verts[3 * (int64_t)vi + 1];
-        xv[k][2] = a.verts[3 * (int64_t)vi + 2];
-      }
-    }
-#pragma unroll
-    for (int o = 0; o < NOUT; ++o) sigma[o] = a.dens[o][e * a.dstride];
-    cx = a.box_center[3 * (int64_t)key];
-    cy = a.box_center[3 * (int64_t)key + 1];
-    cz = a.box_center[3 * (int64_t)key + 2];
-  }
-  if (ok) {
-    bool fin = isfinite(cx) && isfinite(cy) && isfinite(cz);
-#pragma unroll
-    for (int o = 0; o < NOUT; ++o) fin = fin && isfinite(sigma[o]);
-#pragma unroll
-    for (int k = 0; k < NV; ++k) fin = fin && isfinite(xv[k][0]) && isfinite(xv[k][1]) && isfinite(xv[k][2]);
-    if (!fin) {
-      ok = false;
-      flag |= Q2X_FLAG_NONFINITE;
-    }
-  }
-  // Jacobian (Eq. (9)) and unit normal from the absolute vertices
-  double J = 0.0, nx = 0.0, ny = 0.0, nz = 0.0;
-  if (ok) {
-    const double ux = xv[1][0] - xv[0][0], uy = xv[1][1] - xv[0][1], uz = xv[1][2] - xv[0][2];
-    static_assert(NV >= 2 && NV <= 4, "segments, triangles or tetrahedra");
-    if constexpr (NV == 2) {  // segment: length
-      J = sqrt(ux * ux + uy * uy + uz * uz);
-    } else {
-      const double vx = xv[2][0] - xv[0][0], vy = xv[2][1] - xv[0][1], vz = xv[2][2] - xv[0][2];
-      double crx, cry, crz;
-      cross_nofma(ux, uy, uz, vx, vy, vz, crx, cry, crz);
-      if constexpr (NV == 4) {  // tetrahedron: |det|
-        const double wx = xv[3][0] - xv[0][0], wy = xv[3][1] - xv[0][1], wz = xv[3][2] - xv[0][2];
-        J = fabs(crx * wx + cry * wy + crz * wz);
-      } else {
-        J = sqrt(crx * crx + cry * cry + crz * crz);
-        if (J > 0.0) {
-          nx = crx / J;
-          ny = cry / J;
-          nz = crz / J;
-        }
-      }
-    }
-  }
+  for (int o = 0; o < NOUT; ++o) sigma[o] = box_ok ? a.dens[o][e * a.dstride] : 0.0;
+  const ElemGeom<NV, T> gm = element_geometry<NV, T, SCALED>(a.verts, a.n_verts, a.elems, e, a.box_center, key,
+                                                             box_ok, sigma, NOUT);
+  const bool ok = gm.ok;
+  uint32_t flag = gm.flag;
+  const double J = gm.J, nx = gm.nx, ny = gm.ny, nz = gm.nz, scl = gm.scl;
   const bool degenerate = ok && !(J > 0.0);
-
-  // element scale a_e (FP32 path) and the recursion's vertex data
-  double X[NV][3];
-  double amax2 = 0.0;
-#pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    X[k][0] = ok ? xv[k][0] - cx : 0.0;
-    X[k][1] = ok ? xv[k][1] - cy : 0.0;
-    X[k][2] = ok ? xv[k][2] - cz : 0.0;
-    amax2 = fmax(amax2, X[k][0] * X[k][0] + X[k][1] * X[k][1] + X[k][2] * X[k][2]);
-  }
-  double scl = 1.0;
-  if constexpr (SCALED) {
-    scl = sqrt(amax2);
-    if (!(scl > 0.0)) scl = 1.0;
-  }
-  const double inv_scl = 1.0 / scl;
-  T vxr[NV], vxi[NV], vz[NV], vxr2[NV], vxi2[NV];
-#pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    vxr[k] = (T)(0.5 * X[k][0] * inv_scl);
-    vxi[k] = (T)(0.5 * X[k][1] * inv_scl);
-    vz[k] = (T)(X[k][2] * inv_scl);
-    vxr2[k] = (T)(X[k][0] * inv_scl);
-    vxi2[k] = (T)(X[k][1] * inv_scl);
-  }
+  const T* vxr = gm.vxr;
+  const T* vxi = gm.vxi;
+  const T* vz = gm.vz;
+  const T* vxr2 = gm.vxr2;
+  const T* vxi2 = gm.vxi2;
   // s_e = sigma_e J / (4 pi) (Sec. 3.2, Eq. (20)); 0 for skipped elements
   double sw[NOUT];
   static_for<0, NOUT>([&](auto OO) Q2X_INLINE {

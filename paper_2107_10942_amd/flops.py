@@ -91,6 +91,25 @@ def launch_bytes(kind: int, p: int, n_elems: int, n_boxes_occupied: int) -> int:
     return per_elem * n_elems + NOUT[kind] * 16 * (p + 1) ** 2 * n_boxes_occupied
 
 
+def eval_element_flops(kind: int, p: int) -> int:
+    """Receiving side (q2x_eval), per element: geometry + the same recursion +
+    per degree the FP64 weight (2) and per order m >= 0 the weighted value (2),
+    L^m t (6), L^{-m} conj(t) for m > 0 (8) and the (-i)^m accumulation (2),
+    + the final J factor (2).  The double layer has no degree 0."""
+    f = GEOMETRY_FLOPS + recursion_flops(kind, p) + 2
+    for n in range(1 if kind == TRI_DOUBLE else 0, p + 1):
+        f += 2 + 10 + 18 * n
+    return f
+
+
+def eval_launch_bytes(kind: int, p: int, n_elems: int, n_boxes_occupied: int) -> int:
+    """Algorithmic bytes of one q2x_eval launch: per element its vertex indices,
+    vertices, box id, permutation entry and complex result; each occupied box's
+    local coefficients read once."""
+    per_elem = 4 * NV[kind] + 24 * NV[kind] + 4 + 4 + 16
+    return per_elem * n_elems + 16 * (p + 1) ** 2 * n_boxes_occupied
+
+
 # MI355X vector-ALU peak.  256 CUs x 4 SIMDs x 16 lanes = 4096 FMA lanes per
 # clock at 2.4 GHz.  FP64 FMA issues at full rate: 4096 x 2 x 2.4e9 = 78.6
 # TFLOP/s.  Non-packed FP32 FMA issues at the same rate (78.6); the 157.3

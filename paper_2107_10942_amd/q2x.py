@@ -27,7 +27,8 @@ FLAG_BAD_BOX, FLAG_NONFINITE, FLAG_RESERVED, FLAG_BAD_VERTEX, FLAG_NOT_SORTED = 
 EXPORTS = ("q2x_workspace_bytes", "q2x_bucket_workspace_bytes", "q2x_bucket", "q2x_tri_single", "q2x_tri_double", "q2x_segment", "q2x_tet",
            "q2x_tri_both", "q2x_segment_vec", "q2x_status_get", "q2x_status_string", "q2x_profile_enable", "q2x_profile_reset",
            "q2x_profile_read", "q2x_version", "q2x_batch_plan", "q2x_batch_workspace_bytes", "q2x_batch_run", "q2x_batch_launch",
-           "q2x_batch_job_status", "q2x_batch_groups", "q2x_batch_mode", "q2x_batch_destroy")
+           "q2x_batch_job_status", "q2x_batch_groups", "q2x_batch_mode", "q2x_batch_destroy",
+           "q2x_eval_workspace_bytes", "q2x_eval")
 
 
 class Q2XError(RuntimeError):
@@ -98,6 +99,10 @@ def lib():
         L.q2x_batch_mode.restype = ci
         L.q2x_batch_destroy.argtypes = [vp]
         L.q2x_batch_destroy.restype = None
+        L.q2x_eval_workspace_bytes.argtypes = [i64, i64]
+        L.q2x_eval_workspace_bytes.restype = sz
+        L.q2x_eval.argtypes = [ci, vp, i64, vp, i64, vp, vp, i64, vp, ci, ci, cu, vp, vp, sz, vp]
+        L.q2x_eval.restype = ci
         _lib = L
     return _lib
 
@@ -335,6 +340,47 @@ def segment_vec(verts, segs, density3, elem_box, box_center, box_radius, p, prec
                                _ptr(box_radius, torch.float64, "box_radius"), nb, int(p), int(precision), int(norm),
                                flags, _ptr(out, torch.float64, "out"), ctypes.c_void_p(workspace.data_ptr()),
                                workspace.numel(), _stream(stream))
+    _check(rc)
+    return out
+
+
+def eval_workspace_bytes(n_elems, n_boxes) -> int:
+    return int(lib().q2x_eval_workspace_bytes(int(n_elems), int(n_boxes)))
+
+
+def alloc_eval_workspace(n_elems, n_boxes, device=None):
+    nbytes = eval_workspace_bytes(n_elems, n_boxes)
+    if nbytes == 0:
+        raise Q2XError("invalid workspace request")
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device or "cuda")
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + nbytes]
+
+
+def evaluate(kind, verts, elems, elem_box, box_center, local, p, precision=FP32_MIXED, accumulate=False,
+             presorted=False, out=None, workspace=None, stream=None):
+    """Receiving side (q2x_eval): per element, sum_{n<=p,m} L_b[n,m] int_e R_n^m(y - c_b)
+    (double layer: n . grad R).  local [B, (p+1)^2, 2] float64; returns out [N, 2] float64."""
+    if kind not in (TRI_SINGLE, TRI_DOUBLE, SEGMENT, TET):
+        raise Q2XError("evaluate takes TRI_SINGLE, TRI_DOUBLE, SEGMENT or TET")
+    n_el = int(elems.shape[0]) if elems is not None else 0
+    nb = int(box_center.shape[0])
+    if elems is not None and elems.dim() == 2 and elems.shape[1] != VERTS_PER_KIND[kind]:
+        raise Q2XError(f"elements of kind {KIND_NAMES[kind]} need {VERTS_PER_KIND[kind]} vertices")
+    if local is not None and tuple(local.shape) != (nb, (p + 1) ** 2, 2):
+        raise Q2XError(f"local must have shape {(nb, (p + 1) ** 2, 2)}")
+    if out is None:
+        out = torch.empty((n_el, 2), dtype=torch.float64, device=verts.device)
+    elif tuple(out.shape) != (n_el, 2):
+        raise Q2XError(f"out must have shape {(n_el, 2)}")
+    if workspace is None:
+        workspace = alloc_eval_workspace(n_el, nb, device=verts.device)
+    flags = (ACCUMULATE if accumulate else 0) | (PRESORTED if presorted else 0)
+    rc = lib().q2x_eval(int(kind), _ptr(verts, torch.float64, "verts"), int(verts.shape[0]),
+                        _ptr(elems, torch.int32, "elems"), n_el, _ptr(elem_box, torch.int32, "elem_box"),
+                        _ptr(box_center, torch.float64, "box_center"), nb, _ptr(local, torch.float64, "local"),
+                        int(p), int(precision), flags, _ptr(out, torch.float64, "out"),
+                        ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream(stream))
     _check(rc)
     return out
 

@@ -105,3 +105,26 @@ def test_workspace_bytes_and_argument_errors():
     L.q2x_batch_destroy(None)
     assert L.q2x_status_string(-2).startswith(b"Q2X_ERR_P_RANGE")
     assert b"gfx950" in L.q2x_version()
+
+
+def test_eval_argument_errors():
+    """q2x_eval: kinds other than the four element kinds, p out of range, bad
+    precision or flags, missing arrays and a short workspace are refused
+    synchronously, before any device work."""
+    _ensure_built()
+    from paper_2107_10942_amd import q2x
+    L = q2x.lib()
+    vp = ctypes.c_void_p
+    ws = q2x.eval_workspace_bytes(1000, 50)
+    assert ws > 0 and q2x.eval_workspace_bytes(-1, 5) == 0
+    assert q2x.eval_workspace_bytes(5000, 50) >= ws
+
+    def call(kind=0, p=8, prec=0, flags=0, nel=1, local=vp(8), out=vp(8), wsb=ws, wsp=vp(256)):
+        return L.q2x_eval(kind, vp(8), 3, vp(4), nel, vp(4), vp(8), 1, local, p, prec, flags, out, wsp, wsb, None)
+
+    assert call(kind=q2x.TRI_BOTH) == -1 and call(kind=q2x.SEGMENT_VEC) == -1 and call(kind=-1) == -1
+    assert call(p=33) == -2 and call(p=-1) == -2
+    assert call(prec=2) == -1 and call(flags=4) == -1
+    assert call(local=None) == -1 and call(out=None) == -1
+    assert call(wsb=16) == -3 and call(wsp=vp(264)) == -3 and call(wsp=None) == -3
+    assert call(out=vp(12)) == -1  # misaligned output
