@@ -45,6 +45,7 @@ def lib():
         L.orc_q2x.argtypes = [ci, ci, ci, dp, i64, ip, i64, dp, ip, dp, i64, ci, ci, dp]
         L.orc_element_norms.argtypes = [ci, ci, dp, i64, ip, i64, ip, dp, i64, ci, ci, dp]
         L.orc_eval.argtypes = [ci, ci, dp, i64, ip, i64, ip, dp, i64, dp, ci, ci, dp, dp]
+        L.orc_m2m.argtypes = [ci, ci, dp, dp, ip, i64, dp, i64, dp, dp]
         L.orc_max_threads.argtypes = []
         _lib = L
     return _lib
@@ -175,6 +176,26 @@ def evaluate(kind, p, verts, elems, elem_box, box_center, local, nodes=0, thread
                         out.ctypes.data_as(dp), sc.ctypes.data_as(dp))
     assert rc == 0, rc
     return out[:, 0] + 1j * out[:, 1], sc
+
+
+def m2m(p, child, child_center, child_parent, parent_center, norm=NORM_FMM):
+    """Translate child expansions (complex [n_child][(p+1)^2]) to their parents'
+    centres and sum per parent (addition theorem of R).  Returns
+    (parent coefficients complex [n_parent][(p+1)^2], scale [n_parent][(p+1)^2], skipped)."""
+    cc, pcc = _d(child_center)
+    cp, pcp = _i(child_parent)
+    pc, ppc = _d(parent_center)
+    nchild = cp.shape[0]
+    npar = pc.reshape(-1, 3).shape[0]
+    ch = np.ascontiguousarray(np.stack([np.real(child), np.imag(child)], axis=-1), dtype=np.float64)
+    assert ch.shape == (nchild, (p + 1) ** 2, 2)
+    out = np.zeros((npar, (p + 1) ** 2, 2))
+    sc = np.zeros((npar, (p + 1) ** 2))
+    dp = ctypes.POINTER(ctypes.c_double)
+    rc = lib().orc_m2m(p, norm, ch.ctypes.data_as(dp), pcc, pcp, nchild, ppc, npar, out.ctypes.data_as(dp),
+                       sc.ctypes.data_as(dp))
+    assert rc >= 0, rc
+    return out[..., 0] + 1j * out[..., 1], sc, rc
 
 
 def element_norms(kind, p, verts, elems, elem_box, box_center, nodes=0, threads=0):

@@ -584,3 +584,73 @@ int orc_max_threads(void) {
   return 1;
 #endif
 }
+
+/*
+ * Multipole-to-multipole translation (the upward pass of the FMM that
+ * consumes the box coefficients; Sec. 1-2).  R_n^m is a homogeneous harmonic
+ * polynomial whose derivatives are again R's (Sec. 3.2, Eq. (15)); Taylor
+ * expansion of R_n^m(u + t) in t therefore gives the finite addition theorem
+ *   R_n^m(u + t) = sum_{k=0}^{n} sum_{l=-k}^{k} R_k^l(u) R_{n-k}^{m-l}(t)
+ * (terms with |m - l| > n - k are zero).  Applied to y - c_p = (y - c_c) +
+ * (c_c - c_p) inside the definition of the coefficients:
+ *   MOMENT: M_n^m(c_p) = sum_{k,l} M_k^l(c_c) R_{n-k}^{m-l}(c_c - c_p)
+ *   FMM   : F_n^m(c_p) = sum_{k,l} F_k^l(c_c) (-1)^{n-k} R_{n-k}^{l-m}(c_c - c_p)
+ * (FMM: F_n^m = (1/4pi)(-1)^n int R_n^{-m}, Sec. 3.2 Eq. (14)).  The
+ * translation of an expansion truncated at p is exact for every n <= p.
+ * For every child c with parent child_parent[c] in [0, n_parent):
+ *   out[parent] += translated child coefficients
+ *   scale[parent][n*n+n+m] += sum_{k,l} |coef_k^l| |R_{n-k}^{.}|
+ * All (n, m) of the input are read (no symmetry is assumed).  Children with a
+ * parent id outside [0, n_parent) are skipped (return value counts them).
+ * Sequential over children in index order.
+ */
+int orc_m2m(int p, int norm, const double *child, const double *child_center, const int32_t *child_parent,
+            int64_t n_child, const double *parent_center, int64_t n_parent, double *out, double *scale) {
+  if (p < 0 || p > ORC_PMAX) return -1;
+  const int nc = (p + 1) * (p + 1);
+  memset(out, 0, sizeof(double) * 2 * (size_t)nc * (size_t)n_parent);
+  memset(scale, 0, sizeof(double) * (size_t)nc * (size_t)n_parent);
+  double *R = (double *)malloc(sizeof(double) * 2 * (size_t)nc);
+  if (!R) return -2;
+  int skipped = 0;
+  for (int64_t c = 0; c < n_child; ++c) {
+    const int32_t b = child_parent[c];
+    if (b < 0 || b >= n_parent) {
+      ++skipped;
+      continue;
+    }
+    double t[3];
+    sub3(&child_center[3 * c], &parent_center[3 * (int64_t)b], t);
+    orc_solid_harmonics(p, t[0], t[1], t[2], R, NULL);
+    const double *in = child + 2 * (size_t)nc * (size_t)c;
+    double *o = out + 2 * (size_t)nc * (size_t)b;
+    double *sc = scale + (size_t)nc * (size_t)b;
+    for (int n = 0; n <= p; ++n) {
+      for (int m = -n; m <= n; ++m) {
+        double sr = 0.0, si = 0.0, sa = 0.0;
+        for (int k = 0; k <= n; ++k) {
+          const int j = n - k;
+          for (int l = -k; l <= k; ++l) {
+            const int q = (norm == ORC_NORM_MOMENT) ? (m - l) : (l - m);
+            if (q < -j || q > j) continue;
+            const double ar = in[2 * (k * k + k + l)], ai = in[2 * (k * k + k + l) + 1];
+            double rr = R[2 * (j * j + j + q)], ri = R[2 * (j * j + j + q) + 1];
+            if (norm != ORC_NORM_MOMENT && (j & 1)) {
+              rr = -rr;
+              ri = -ri;
+            }
+            sr += ar * rr - ai * ri;
+            si += ar * ri + ai * rr;
+            sa += sqrt(ar * ar + ai * ai) * sqrt(rr * rr + ri * ri);
+          }
+        }
+        const int oi = n * n + n + m;
+        o[2 * oi] += sr;
+        o[2 * oi + 1] += si;
+        sc[oi] += sa;
+      }
+    }
+  }
+  free(R);
+  return skipped;
+}

@@ -563,3 +563,81 @@ def test_eval_point_source_local_expansion(kind):
         bound = refmath.truncation_bound("double" if kind == "double" else "single", p, mu, a, d)
         assert abs(v.imag) < 1e-14 * sc
         assert abs(v.real - ref) <= bound + 1e-14 * abs(ref) + 1e-15, (kind, p, v, ref, bound)
+
+
+# ----------------------------------------------------------------- M2M (upward pass)
+def _child_parent_setup(kind, n_child=7, n_parent=3, n_el=40, seed=0):
+    """Random elements in child boxes; children assigned to random parents
+    (translation of truncated multipoles is a finite identity: any centres)."""
+    rng = np.random.default_rng(seed)
+    nv = oracle.VERTS_PER_KIND[kind]
+    cc = rng.uniform(-1, 1, (n_child, 3))
+    pc = rng.uniform(-1, 1, (n_parent, 3))
+    cp = np.arange(n_child, dtype=np.int32) % n_parent
+    eb = rng.integers(0, n_child, n_el).astype(np.int32)
+    verts = (cc[eb][:, None, :] + 0.2 * rng.standard_normal((n_el, nv, 3))).reshape(-1, 3)
+    elems = np.arange(n_el * nv, dtype=np.int32).reshape(n_el, nv)
+    dens = rng.uniform(-1, 1, n_el)
+    return verts, elems, dens, eb, cc, cp, pc
+
+
+@pytest.mark.parametrize("norm", [oracle.NORM_FMM, oracle.NORM_MOMENT])
+@pytest.mark.parametrize("kind", ["single", "double", "segment", "tet"])
+def test_m2m_equals_expansion_about_the_parent(kind, norm):
+    """Translating the children's coefficients (addition theorem) gives the
+    coefficients computed directly about the parent's centre by quadrature of
+    R_n^m(y - c_parent): a wrong sign, index or dropped term fails."""
+    code = KINDS[kind]
+    p = 9
+    verts, elems, dens, eb, cc, cp, pc = _child_parent_setup(code, seed=3 + code)
+    child = oracle.q2x(code, p, verts, elems, dens, eb, cc, norm=norm)
+    par, sc, skipped = oracle.m2m(p, child, cc, cp, pc, norm=norm)
+    assert skipped == 0
+    direct = oracle.q2x(code, p, verts, elems, dens, cp[eb], pc, norm=norm)
+    err = np.abs(par - direct) / (sc + np.abs(direct) + 1e-300)
+    assert err.max() < 1e-13, err.max()
+    assert np.abs(direct).max() > 1e-3
+
+
+@pytest.mark.parametrize("norm", [oracle.NORM_FMM, oracle.NORM_MOMENT])
+def test_m2m_point_source_closed_form(norm):
+    """A unit point charge at y has coefficients (1/4pi)(-1)^n R_n^{-m}(y - c)
+    (FMM; MOMENT: R_n^m(y - c)), here from scipy's associated Legendre
+    functions; translated from c_c they must equal the same formula at c_p."""
+    p = 12
+    y = np.array([0.31, -0.12, 0.27])
+    c1 = np.array([0.1, 0.05, -0.2])
+    c2 = np.array([-0.4, 0.3, 0.25])
+
+    def point(c):
+        R = refmath.solid_R_scipy(p, *(y - c))
+        if norm == oracle.NORM_MOMENT:
+            return R
+        F = np.zeros_like(R)
+        for n in range(p + 1):
+            for m in range(-n, n + 1):
+                F[idx(n, m)] = (-1) ** n * R[idx(n, -m)] / (4 * math.pi)
+        return F
+    par, sc, _ = oracle.m2m(p, point(c1)[None], c1[None], np.zeros(1, np.int32), c2[None], norm=norm)
+    ref = point(c2)
+    assert np.max(np.abs(par[0] - ref) / (sc[0] + 1e-300)) < 1e-14
+
+
+def test_m2m_identity_composition_and_skips():
+    """Zero shift is the identity (exactly); c1 -> c2 -> c3 equals c1 -> c3;
+    several children of one parent add; bad parent ids are skipped and counted."""
+    p = 8
+    rng = np.random.default_rng(9)
+    F = rng.uniform(-1, 1, (1, (p + 1) ** 2)) + 1j * rng.uniform(-1, 1, (1, (p + 1) ** 2))
+    c1, c2, c3 = rng.uniform(-1, 1, (3, 3))
+    z = np.zeros(1, np.int32)
+    same, _, _ = oracle.m2m(p, F, c1[None], z, c1[None])
+    assert np.array_equal(same, F)
+    a, _, _ = oracle.m2m(p, F, c1[None], z, c2[None])
+    b, sb, _ = oracle.m2m(p, a, c2[None], z, c3[None])
+    d, sd, _ = oracle.m2m(p, F, c1[None], z, c3[None])
+    assert np.max(np.abs(b - d) / (sd + 1e-300)) < 1e-13
+    two, _, _ = oracle.m2m(p, np.concatenate([F, a]), np.stack([c1, c2]), np.zeros(2, np.int32), c3[None])
+    assert np.max(np.abs(two - 2 * d) / (sd + 1e-300)) < 1e-13
+    bad, _, skipped = oracle.m2m(p, np.concatenate([F, F]), np.stack([c1, c1]), np.array([0, 5], np.int32), c3[None])
+    assert skipped == 1 and np.array_equal(bad, d)
