@@ -281,6 +281,61 @@ def receiving_side(dev, reps=20):
     return res
 
 
+def upward_pass(dev, reps=20):
+    """Q2X leaves of the headline sphere (single layer, p = 16, FP32-mixed) then
+    the M2M upward pass from level 5 to level 2 (q2x_m2m per level, FP64,
+    children presorted in Morton order).  Timed with HIP events."""
+    import torch
+
+    from paper_2107_10942_amd import flops, q2x
+    from q2x_inputs import configs, octree
+    job = configs.perturbed_sphere_pair()[0]
+    p = job.p
+    levels, parents = octree.tree_levels(job.boxes, top=2)
+    v, e, d, eb, bc, br = q2x.job_tensors(job, dev)
+    leaf = q2x.run(job.kind, v, e, d, eb, bc, br, p, precision=q2x.FP32_MIXED)
+    centers = [torch.as_tensor(c, dtype=torch.float64, device=dev) for _, c in levels]
+    pars = [torch.as_tensor(x, dtype=torch.int32, device=dev) for x in parents]
+    outs = [torch.empty((c.shape[0], (p + 1) ** 2, 2), dtype=torch.float64, device=dev) for c in centers[1:]]
+    wss = [q2x.alloc_m2m_workspace(len(x), c.shape[0], device=dev) for x, c in zip(parents, centers[1:])]
+    stream = torch.cuda.current_stream()
+
+    def run_all():
+        src = leaf
+        for i in range(len(parents)):
+            q2x.m2m(src, centers[i], pars[i], centers[i + 1], p, presorted=True, out=outs[i], workspace=wss[i],
+                    stream=stream)
+            src = outs[i]
+    for _ in range(3):
+        run_all()
+    torch.cuda.synchronize()
+    res = {"workload": f"perturbed icosphere k=6 leaves (level 5, {job.n_boxes} boxes) up to level 2, p={p}",
+           "boxes_per_level": [int(c.shape[0]) for c in centers], "levels": []}
+    for i in range(len(parents)):
+        a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        src = leaf if i == 0 else outs[i - 1]
+        a.record(stream)
+        for _ in range(reps):
+            q2x.m2m(src, centers[i], pars[i], centers[i + 1], p, presorted=True, out=outs[i], workspace=wss[i],
+                    stream=stream)
+        z.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(z) / reps
+        nch = len(parents[i])
+        fl = flops.m2m_child_flops(p) * nch
+        res["levels"].append({"children": nch, "parents": int(centers[i + 1].shape[0]), "call_ms": ms,
+                              "translations_per_s": nch / (ms * 1e-3), "tflops": fl / (ms * 1e-3) / 1e12})
+    a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        run_all()
+    z.record(stream)
+    torch.cuda.synchronize()
+    res["upward_pass_ms"] = a.elapsed_time(z) / reps
+    res["status_flags"] = [q2x.status(w)[0] for w in wss]
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -436,6 +491,7 @@ def main():
     if not args.no_configs:
         line["other_workloads"] = other_workloads(dev)
         line["receiving_side"] = receiving_side(dev)
+        line["upward_pass"] = upward_pass(dev)
     if not args.no_batch:
         line["batch_workload"] = batch_workload(dev)
     if not args.no_serving:

@@ -235,6 +235,38 @@ q2x_status q2x_eval(int kind, const double* verts, int64_t n_verts, const int32_
                     void* stream);
 
 /*
+ * Multipole-to-multipole translation: the upward-pass step of the FMM that
+ * consumes the box coefficients (Sec. 1-2).  Each child expansion about its
+ * centre c_c is translated to its parent's centre c_p with the finite
+ * addition theorem of the regular solid harmonics (a consequence of the
+ * derivative relations of Sec. 3.2, Eq. (15)), exact for every n <= p, and
+ * the children of a parent are summed:
+ *   Q2X_NORM_FMM   : F_n^m(c_p) = sum_c sum_{k<=n,l} F_k^l(c_c) R_{n-k}^{l-m}(c_p - c_c)
+ *   Q2X_NORM_MOMENT: M_n^m(c_p) = sum_c sum_{k<=n,l} M_k^l(c_c) R_{n-k}^{m-l}(c_c - c_p)
+ *   child_coeffs  [n_child][(p+1)^2][2] doubles, the layout of the Q2X outputs.
+ *                 Only orders m >= 0 are read: the expansions must satisfy
+ *                 A_n^{-m} = (-1)^m conj(A_n^m) (Sec. 3.2, Eq. (12); every
+ *                 expansion of a real density does, so do all Q2X outputs)
+ *   child_center  [n_child][3];  child_parent [n_child] int32 parent of each child
+ *   parent_center [n_parent][3]
+ *   parent_coeffs [n_parent][(p+1)^2][2] out; every parent is overwritten
+ *                 (parents without children get zeros) unless Q2X_ACCUMULATE;
+ *                 m < 0 written from the symmetry, imag(A_n^0) = 0.  Must not
+ *                 overlap child_coeffs (one call per tree level)
+ *   flags         Q2X_ACCUMULATE; Q2X_PRESORTED (child_parent non-decreasing,
+ *                 as for Morton-ordered boxes: skip the grouping sort; a
+ *                 decrease sets Q2X_FLAG_NOT_SORTED and the result is undefined)
+ * Children with a parent id outside [0, n_parent) set Q2X_FLAG_BAD_BOX,
+ * children whose centre or parent centre is non-finite set
+ * Q2X_FLAG_NONFINITE; both are skipped and counted.  FP64 throughout.
+ * Workspace: q2x_m2m_workspace_bytes(n_child, n_parent) bytes.
+ */
+size_t q2x_m2m_workspace_bytes(int64_t n_child, int64_t n_parent);
+q2x_status q2x_m2m(const double* child_coeffs, const double* child_center, const int32_t* child_parent,
+                   int64_t n_child, const double* parent_center, int64_t n_parent, int p, int norm, unsigned flags,
+                   double* parent_coeffs, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
  * Batches: many meshes (jobs) in one replayed launch sequence.  A job is one
  * single call's arguments; kind may be any q2x_kind (density2/coeffs2 only for
  * Q2X_TRI_BOTH; for Q2X_SEGMENT_VEC density is [N][3] and coeffs [3][B][..]).  Q2X_PRESORTED is accepted and has no effect (the batch always

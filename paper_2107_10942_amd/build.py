@@ -23,7 +23,7 @@ COMMON = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(HERE, "..", "include")]
 
-SIMPLE = ["q2x_api.hip", "q2x_bucket.hip", "q2x_dispatch.hip", "q2x_batch.hip"]
+SIMPLE = ["q2x_api.hip", "q2x_bucket.hip", "q2x_dispatch.hip", "q2x_batch.hip", "q2x_m2m.hip"]
 INST = [(k, f) for k in range(6) for f in (0, 1)]
 EVAL_INST = [(k, f) for k in range(4) for f in (0, 1)]
 
@@ -44,11 +44,11 @@ def _units():
 
 
 def source_hash() -> str:
-    """Short hash of the library sources (ties stored profiler figures to the code they measured)."""
+    """Short hash of the sources of the tile kernel (ties stored profiler
+    figures of that kernel to the code they measured)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("q2x_tile.hpp", "q2x_internal.hpp", "q2x_api.hip", "q2x_bucket.hip", "q2x_dispatch.hip", "q2x_inst.hip",
-              "q2x_batch.hip", "q2x_eval.hpp", "q2x_eval_inst.hip"):
+    for f in ("q2x_tile.hpp", "q2x_internal.hpp", "q2x_inst.hip"):
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

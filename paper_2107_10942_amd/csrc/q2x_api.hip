@@ -13,7 +13,8 @@ namespace q2x {
 
 hipError_t bucket_elements(const int32_t* elem_box, int64_t n, int64_t nb, int32_t* scratch, Status* status,
                            hipStream_t s, const int32_t** keys_out, const int32_t** perm_out);
-hipError_t launch_box_bounds(const int32_t* keys, int64_t n, int64_t nb, int32_t* box_start, hipStream_t s);
+hipError_t launch_box_bounds(const int32_t* keys, int64_t n, int64_t nb, int32_t* box_start, hipStream_t s,
+                             Status* order_check);
 hipError_t clear_status(Status* st, hipStream_t s);
 hipError_t copy_words(int32_t* dst, const int32_t* src, int64_t n, hipStream_t s);
 size_t bucket_scratch_bytes(int64_t n, int64_t nb);
@@ -320,6 +321,66 @@ q2x_status q2x_eval(int kind, const double* verts, int64_t n_verts, const int32_
   return Q2X_OK;
 }
 
+size_t q2x_m2m_workspace_bytes(int64_t n_child, int64_t n_parent) {
+  if (n_child < 0 || n_parent < 0) return 0;
+  return align_up(sizeof(Status)) + align_up((size_t)(n_parent + 1) * sizeof(int32_t)) +
+         align_up(bucket_scratch_bytes(n_child, n_parent));
+}
+
+q2x_status q2x_m2m(const double* child_coeffs, const double* child_center, const int32_t* child_parent,
+                   int64_t n_child, const double* parent_center, int64_t n_parent, int p, int norm, unsigned flags,
+                   double* parent_coeffs, void* workspace, size_t workspace_bytes, void* stream) {
+  if (p < 0 || p > Q2X_P_MAX) return Q2X_ERR_P_RANGE;
+  if (n_child < 0 || n_parent < 0 || n_child >= ((int64_t)1 << 31) - 64 || n_parent >= ((int64_t)1 << 31) - 1)
+    return Q2X_ERR_ARG;
+  if (norm != Q2X_NORM_FMM && norm != Q2X_NORM_MOMENT) return Q2X_ERR_ARG;
+  if (flags & ~(unsigned)(Q2X_ACCUMULATE | Q2X_PRESORTED)) return Q2X_ERR_ARG;
+  if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return Q2X_ERR_WORKSPACE;
+  if (n_child > 0 && (!child_coeffs || !child_center || !child_parent)) return Q2X_ERR_ARG;
+  if (n_parent > 0 && (!parent_center || !parent_coeffs)) return Q2X_ERR_ARG;
+  if (((uintptr_t)child_coeffs % 8) || ((uintptr_t)child_center % 8) || ((uintptr_t)child_parent % 4) ||
+      ((uintptr_t)parent_center % 8) || ((uintptr_t)parent_coeffs % 8))
+    return Q2X_ERR_ARG;
+  const size_t row = (size_t)(p + 1) * (size_t)(p + 1) * 2 * sizeof(double);
+  if (n_child > 0 && n_parent > 0) {  // the parents' rows are written while the children's are read
+    const uintptr_t c0 = (uintptr_t)child_coeffs, c1 = c0 + row * (size_t)n_child;
+    const uintptr_t p0 = (uintptr_t)parent_coeffs, p1 = p0 + row * (size_t)n_parent;
+    if (c0 < p1 && p0 < c1) return Q2X_ERR_ARG;
+  }
+  if (workspace_bytes < q2x_m2m_workspace_bytes(n_child, n_parent)) return Q2X_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  Status* st = (Status*)ws;
+  int32_t* box_start = (int32_t*)(ws + align_up(sizeof(Status)));
+  int32_t* scratch = (int32_t*)(ws + align_up(sizeof(Status)) + align_up((size_t)(n_parent + 1) * sizeof(int32_t)));
+  const bool presorted = (flags & Q2X_PRESORTED) != 0;
+  const int32_t* keys = child_parent;
+  const int32_t* perm = nullptr;
+  hipError_t err;
+  if (presorted || n_child == 0) err = clear_status(st, s);
+  else err = bucket_elements(child_parent, n_child, n_parent, scratch, st, s, &keys, &perm);
+  if (err != hipSuccess) return Q2X_ERR_HIP;
+  if (n_parent == 0) return Q2X_OK;
+  if (launch_box_bounds(keys, n_child, n_parent, box_start, s, presorted ? st : nullptr) != hipSuccess)
+    return Q2X_ERR_HIP;
+  M2MArgs a{};
+  a.child = child_coeffs;
+  a.child_center = child_center;
+  a.perm = perm;
+  a.box_start = box_start;
+  a.parent_center = parent_center;
+  a.out = parent_coeffs;
+  a.status = st;
+  a.n_child = n_child;
+  a.n_parent = n_parent;
+  a.p = p;
+  a.norm = norm;
+  a.accumulate = (flags & Q2X_ACCUMULATE) ? 1 : 0;
+  a.presorted_bad = (presorted && n_child > 0) ? 1 : 0;
+  if (launch_m2m(a, s) != hipSuccess) return Q2X_ERR_HIP;
+  return Q2X_OK;
+}
+
 size_t q2x_bucket_workspace_bytes(int64_t n_elems, int64_t n_boxes) {
   if (n_elems < 0 || n_boxes < 0) return 0;
   return align_up(sizeof(Status)) + align_up(bucket_scratch_bytes(n_elems, n_boxes));
@@ -343,7 +404,7 @@ q2x_status q2x_bucket(const int32_t* elem_box, int64_t n_elems, int64_t n_boxes,
   } else if (bucket_elements(elem_box, n_elems, n_boxes, scratch, st, s, &keys, &pm) != hipSuccess) {
     return Q2X_ERR_HIP;
   }
-  if (launch_box_bounds(keys, n_elems, n_boxes, box_start, s) != hipSuccess) return Q2X_ERR_HIP;
+  if (launch_box_bounds(keys, n_elems, n_boxes, box_start, s, nullptr) != hipSuccess) return Q2X_ERR_HIP;
   if (n_elems > 0 && copy_words(perm, pm, n_elems, s) != hipSuccess) return Q2X_ERR_HIP;
   return Q2X_OK;
 }

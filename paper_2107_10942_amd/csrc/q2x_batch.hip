@@ -31,7 +31,8 @@
 namespace q2x {
 hipError_t bucket_elements(const int32_t* elem_box, int64_t n, int64_t nb, int32_t* scratch, Status* status,
                            hipStream_t s, const int32_t** keys_out, const int32_t** perm_out);
-hipError_t launch_box_bounds(const int32_t* keys, int64_t n, int64_t nb, int32_t* box_start, hipStream_t s);
+hipError_t launch_box_bounds(const int32_t* keys, int64_t n, int64_t nb, int32_t* box_start, hipStream_t s,
+                             Status* order_check);
 size_t bucket_scratch_bytes(int64_t n, int64_t nb);
 
 namespace {
@@ -182,7 +183,7 @@ hipError_t enqueue(q2x_plan* P, char* ws, const char* tab, int mode, hipStream_t
     hipError_t e = bucket_elements(keys, P->n_total, P->total_boxes, sort_scratch, st + P->n_jobs, s, &skeys, &sperm);
     if (e != hipSuccess) return e;
   }
-  hipError_t e = launch_box_bounds(skeys, P->n_total, P->total_boxes, box_start, s);
+  hipError_t e = launch_box_bounds(skeys, P->n_total, P->total_boxes, box_start, s, nullptr);
   if (e != hipSuccess) return e;
   hipEvent_t* ev = P->evs.data();
   const bool par = (mode == 1) && P->groups.size() > 1;

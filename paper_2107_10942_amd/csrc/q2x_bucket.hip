@@ -178,8 +178,10 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter(const int32_t* __r
 }
 
 // box_start[b] = first sorted position whose key >= b, for b in [0, B];
-// keys outside [0, B) count as -1 (before everything) or B (after).
-__global__ void box_bounds(const int32_t* __restrict__ keys, int64_t n, int64_t nb, int32_t* __restrict__ box_start) {
+// keys outside [0, B) count as -1 (before everything) or B (after).  With
+// `order_check`, a decrease of the (clamped) keys sets Q2X_FLAG_NOT_SORTED.
+__global__ void box_bounds(const int32_t* __restrict__ keys, int64_t n, int64_t nb, int32_t* __restrict__ box_start,
+                           Status* order_check) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i > n) return;
   auto ck = [&](int64_t j) -> int64_t {
@@ -188,6 +190,7 @@ __global__ void box_bounds(const int32_t* __restrict__ keys, int64_t n, int64_t 
   };
   const int64_t k = (i < n) ? ck(i) : nb;
   const int64_t kp = (i == 0) ? -1 : ck(i - 1);
+  if (order_check && kp > k) atomicOr(&order_check->flags, (uint32_t)Q2X_FLAG_NOT_SORTED);
   for (int64_t b = kp + 1; b <= k; ++b) box_start[b] = (int32_t)i;
 }
 
@@ -250,9 +253,10 @@ hipError_t bucket_elements(const int32_t* elem_box, int64_t n, int64_t nb, int32
   return hipGetLastError();
 }
 
-hipError_t launch_box_bounds(const int32_t* keys, int64_t n, int64_t nb, int32_t* box_start, hipStream_t s) {
+hipError_t launch_box_bounds(const int32_t* keys, int64_t n, int64_t nb, int32_t* box_start, hipStream_t s,
+                             Status* order_check) {
   const unsigned nbl = (unsigned)((n + 1 + 255) / 256);
-  hipLaunchKernelGGL(box_bounds, dim3(nbl), dim3(256), 0, s, keys, n, nb, box_start);
+  hipLaunchKernelGGL(box_bounds, dim3(nbl), dim3(256), 0, s, keys, n, nb, box_start, order_check);
   return hipGetLastError();
 }
 

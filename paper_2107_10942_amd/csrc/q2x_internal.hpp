@@ -94,6 +94,23 @@ struct EvalArgs {
   int count_bad_ids;     // presorted input (no bucketing pass): count ids outside [0, n_boxes) here
 };
 
+// Arguments of the multipole-to-multipole kernel (one workgroup per parent).
+struct M2MArgs {
+  const double* child;         // [n_child][(p+1)^2][2] child expansions (orders m >= 0 read)
+  const double* child_center;  // [n_child][3]
+  const int32_t* perm;         // sorted position -> child (nullptr: identity)
+  const int32_t* box_start;    // [n_parent + 1] first sorted position of each parent's children
+  const double* parent_center; // [n_parent][3]
+  double* out;                 // [n_parent][(p+1)^2][2]
+  Status* status;
+  int64_t n_child;
+  int64_t n_parent;
+  int p;
+  int norm;
+  int accumulate;
+  int presorted_bad;           // presorted input: count the ids outside [0, n_parent) from box_start
+};
+
 // Arguments of the fix-up kernel (boxes cut by tile edges, empty boxes).
 struct FixupArgs {
   const int32_t* box_start;  // written by the tile kernel (unused when n_pos == 0)
@@ -217,4 +234,5 @@ namespace q2x {
 hipError_t launch_tiles(int kind, int prec, int P, const TileArgs& a, int64_t n_tiles, hipStream_t s);
 int bucket_order(int p);  // smallest compiled bucket >= p (or -1)
 hipError_t launch_eval(int kind, int prec, int P, const EvalArgs& a, int64_t n_tiles, hipStream_t s);
+hipError_t launch_m2m(const M2MArgs& a, hipStream_t s);
 }  // namespace q2x

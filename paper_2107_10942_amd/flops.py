@@ -110,6 +110,21 @@ def eval_launch_bytes(kind: int, p: int, n_elems: int, n_boxes_occupied: int) ->
     return per_elem * n_elems + 16 * (p + 1) ** 2 * n_boxes_occupied
 
 
+def m2m_child_flops(p: int) -> int:
+    """One child-to-parent translation (q2x_m2m): every output (n, m >= 0) sums
+    A_k^l R_{n-k}^{l-m} over k <= n and |l| <= k, |l - m| <= n - k, one complex
+    multiply-add (4 FMAs = 8 FLOPs) each; plus the ladder for R of the shift
+    (~10 FLOPs per (j, q)).  Expansions are read once per child."""
+    macs = 0
+    for n in range(p + 1):
+        for m in range(n + 1):
+            for k in range(n + 1):
+                j = n - k
+                lo, hi = max(-k, m - j), min(k, m + j)
+                macs += max(0, hi - lo + 1)
+    return 8 * macs + 10 * (p + 1) * (p + 2) // 2
+
+
 # MI355X vector-ALU peak.  256 CUs x 4 SIMDs x 16 lanes = 4096 FMA lanes per
 # clock at 2.4 GHz.  FP64 FMA issues at full rate: 4096 x 2 x 2.4e9 = 78.6
 # TFLOP/s.  Non-packed FP32 FMA issues at the same rate (78.6); the 157.3

@@ -28,7 +28,7 @@ EXPORTS = ("q2x_workspace_bytes", "q2x_bucket_workspace_bytes", "q2x_bucket", "q
            "q2x_tri_both", "q2x_segment_vec", "q2x_status_get", "q2x_status_string", "q2x_profile_enable", "q2x_profile_reset",
            "q2x_profile_read", "q2x_version", "q2x_batch_plan", "q2x_batch_workspace_bytes", "q2x_batch_run", "q2x_batch_launch",
            "q2x_batch_job_status", "q2x_batch_groups", "q2x_batch_mode", "q2x_batch_destroy",
-           "q2x_eval_workspace_bytes", "q2x_eval")
+           "q2x_eval_workspace_bytes", "q2x_eval", "q2x_m2m_workspace_bytes", "q2x_m2m")
 
 
 class Q2XError(RuntimeError):
@@ -103,6 +103,10 @@ def lib():
         L.q2x_eval_workspace_bytes.restype = sz
         L.q2x_eval.argtypes = [ci, vp, i64, vp, i64, vp, vp, i64, vp, ci, ci, cu, vp, vp, sz, vp]
         L.q2x_eval.restype = ci
+        L.q2x_m2m_workspace_bytes.argtypes = [i64, i64]
+        L.q2x_m2m_workspace_bytes.restype = sz
+        L.q2x_m2m.argtypes = [vp, vp, vp, i64, vp, i64, ci, ci, cu, vp, vp, sz, vp]
+        L.q2x_m2m.restype = ci
         _lib = L
     return _lib
 
@@ -382,6 +386,47 @@ def evaluate(kind, verts, elems, elem_box, box_center, local, p, precision=FP32_
                         int(p), int(precision), flags, _ptr(out, torch.float64, "out"),
                         ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream(stream))
     _check(rc)
+    return out
+
+
+def alloc_m2m_workspace(n_child, n_parent, device=None):
+    nbytes = int(lib().q2x_m2m_workspace_bytes(int(n_child), int(n_parent)))
+    if nbytes == 0:
+        raise Q2XError("invalid workspace request")
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device or "cuda")
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + nbytes]
+
+
+def m2m(child, child_center, child_parent, parent_center, p, norm=NORM_FMM, accumulate=False, presorted=False,
+        out=None, workspace=None, stream=None):
+    """Translate child expansions [C, (p+1)^2, 2] to their parents' centres and sum
+    per parent (q2x_m2m); returns out [P, (p+1)^2, 2] float64."""
+    nc = int(child_parent.shape[0])
+    npar = int(parent_center.shape[0])
+    if child is not None and tuple(child.shape) != (nc, (p + 1) ** 2, 2):
+        raise Q2XError(f"child must have shape {(nc, (p + 1) ** 2, 2)}")
+    out = _out(out, npar, p, parent_center.device)
+    if workspace is None:
+        workspace = alloc_m2m_workspace(nc, npar, device=parent_center.device)
+    flags = (ACCUMULATE if accumulate else 0) | (PRESORTED if presorted else 0)
+    rc = lib().q2x_m2m(_ptr(child, torch.float64, "child"), _ptr(child_center, torch.float64, "child_center"),
+                       _ptr(child_parent, torch.int32, "child_parent"), nc,
+                       _ptr(parent_center, torch.float64, "parent_center"), npar, int(p), int(norm), flags,
+                       _ptr(out, torch.float64, "out"), ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                       _stream(stream))
+    _check(rc)
+    return out
+
+
+def upward(leaf, centers, parents, p, norm=NORM_FMM, stream=None):
+    """Upward pass: `leaf` [B0, (p+1)^2, 2] about centers[0]; centers[i] [B_i, 3]
+    for levels i = 0 (leaves) .. L; parents[i] [B_i] int32 (non-decreasing)
+    maps level i to level i + 1.  One q2x_m2m call per level; returns the list
+    of expansions, leaves first."""
+    out = [leaf]
+    for i, par in enumerate(parents):
+        out.append(m2m(out[-1], centers[i], par, centers[i + 1], p, norm=norm, presorted=True, stream=stream))
     return out
 
 

@@ -72,3 +72,39 @@ def assign(verts, elems, level: int, half: float | None = None) -> Boxes:
     radius = np.full(ucode.shape[0], np.sqrt(3.0) * h / 2.0)
     return Boxes(level=level, lo=lo, half=half, h=h, elem_box=inv.astype(np.int32), center=center,
                  radius=radius, morton=ucode, counts=counts.astype(np.int64))
+
+
+def _compact3(x):
+    """Inverse of _spread3: gather every third bit of x into the low 21 bits."""
+    x = x.astype(np.uint64) & np.uint64(0x1249249249249249)
+    x = (x | (x >> np.uint64(2))) & np.uint64(0x10C30C30C30C30C3)
+    x = (x | (x >> np.uint64(4))) & np.uint64(0x100F00F00F00F00F)
+    x = (x | (x >> np.uint64(8))) & np.uint64(0x1F0000FF0000FF)
+    x = (x | (x >> np.uint64(16))) & np.uint64(0x1F00000000FFFF)
+    x = (x | (x >> np.uint64(32))) & np.uint64(0x1FFFFF)
+    return x.astype(np.int64)
+
+
+def box_centers(morton, level: int, lo: float, half: float):
+    """Centres of the boxes with the given Morton codes at a level."""
+    m = np.asarray(morton, dtype=np.int64).astype(np.uint64)
+    ijk = np.stack([_compact3(m), _compact3(m >> np.uint64(1)), _compact3(m >> np.uint64(2))], 1)
+    h = 2.0 * half / (1 << level)
+    return lo + (ijk + 0.5) * h
+
+
+def tree_levels(boxes: Boxes, top: int = 2):
+    """The occupied boxes of every level from the leaves up to `top`: a list,
+    leaves first, of (morton, center) per level and, per level below the top,
+    child_parent (index of each box's parent in the next list).  Parents are
+    numbered in Morton order, so child_parent is non-decreasing."""
+    levels = [(boxes.morton, boxes.center)]
+    parents = []
+    code = boxes.morton
+    for lev in range(boxes.level - 1, top - 1, -1):
+        pc = code >> 3
+        ucode, inv = np.unique(pc, return_inverse=True)
+        parents.append(inv.astype(np.int32))
+        levels.append((ucode, box_centers(ucode, lev, boxes.lo, boxes.half)))
+        code = ucode
+    return levels, parents
