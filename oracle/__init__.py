@@ -46,6 +46,8 @@ def lib():
         L.orc_element_norms.argtypes = [ci, ci, dp, i64, ip, i64, ip, dp, i64, ci, ci, dp]
         L.orc_eval.argtypes = [ci, ci, dp, i64, ip, i64, ip, dp, i64, dp, ci, ci, dp, dp]
         L.orc_m2m.argtypes = [ci, ci, dp, dp, ip, i64, dp, i64, dp, dp]
+        L.orc_near_one.argtypes = [dp, dp, dp, dp, ci, dp, dp]
+        L.orc_near.argtypes = [dp, i64, ip, i64, dp, i64, lp, ip, ci, ci, dp, dp]
         L.orc_max_threads.argtypes = []
         _lib = L
     return _lib
@@ -196,6 +198,38 @@ def m2m(p, child, child_center, child_parent, parent_center, norm=NORM_FMM):
                        sc.ctypes.data_as(dp))
     assert rc >= 0, rc
     return out[..., 0] + 1j * out[..., 1], sc, rc
+
+
+def near_one(r, xv, k=24):
+    """Single- and double-layer potentials (L, M) of the unit-density triangle
+    xv [3][3] at the point r (polar quadrature about the projection of r)."""
+    r, pr = _d(r)
+    xv = np.ascontiguousarray(xv, dtype=np.float64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    L = ctypes.c_double(0.0)
+    M = ctypes.c_double(0.0)
+    rc = lib().orc_near_one(pr, xv[0].ctypes.data_as(dp), xv[1].ctypes.data_as(dp), xv[2].ctypes.data_as(dp), k,
+                            ctypes.byref(L), ctypes.byref(M))
+    assert rc == 0, rc
+    return L.value, M.value
+
+
+def near(verts, tris, targets, pair_start, pair_tri, k=24, threads=0):
+    """Per (target, triangle) pair in CSR order: (L [P], M [P]) of unit density."""
+    verts, pv = _d(verts)
+    tris, pt = _i(tris)
+    targets, ptg = _d(targets)
+    pair_start, pps = _l(pair_start)
+    pair_tri, ppt = _i(pair_tri)
+    npair = pair_tri.shape[0]
+    L = np.zeros(npair)
+    M = np.zeros(npair)
+    dp = ctypes.POINTER(ctypes.c_double)
+    rc = lib().orc_near(pv, verts.reshape(-1, 3).shape[0], pt, tris.reshape(-1, 3).shape[0], ptg,
+                        targets.reshape(-1, 3).shape[0], pps, ppt, k, threads, L.ctypes.data_as(dp),
+                        M.ctypes.data_as(dp))
+    assert rc == 0, rc
+    return L, M
 
 
 def element_norms(kind, p, verts, elems, elem_box, box_center, nodes=0, threads=0):

@@ -654,3 +654,146 @@ int orc_m2m(int p, int norm, const double *child, const double *child_center, co
   free(R);
   return skipped;
 }
+
+/*
+ * Near field: the single- and double-layer potentials of one flat triangle
+ * with unit density at a point r (the integrals L and M of Sec. 4.1,
+ * Eq. (63), which the paper evaluates in closed form; computed here WITHOUT
+ * that formula):
+ *   L(r) = int_T G(r, y) dS_y,   M(r) = int_T dG/dn_y dS_y = int_T hs / (4 pi |r - y|^3) dS_y,
+ * G = 1/(4 pi |r - y|), n the unit normal (x2 - x1) x (x3 - x1) / |.|, hs =
+ * (r - x1) . n the signed height, h = |hs|.  The triangle is split at the
+ * projection r0 = r - hs n into the three triangles (r0, x_q, x_q+1), signed
+ * by orientation, and each is integrated in polar coordinates about r0.  The
+ * radial integrals are elementary:
+ *   int_0^rho s ds / sqrt(s^2 + h^2)          = rho^2 / (R + h),        R = sqrt(rho^2 + h^2)
+ *   int_0^rho hs s ds / (s^2 + h^2)^(3/2)     = sign(hs) rho^2 / (R (R + h))
+ * and along an edge y(t) = a + t (b - a) the angle element is
+ * dphi = A2 / rho(t)^2 dt, A2 = ((a - r0) x (b - a)) . n, so
+ *   L = (1/4pi) sum_edges A2 int_0^1 dt / (R(t) + h)
+ *   M = (1/4pi) sign(hs) sum_edges A2 int_0^1 dt / (R(t) (R(t) + h)).
+ * The t-integrals use Gauss-Legendre (k nodes) on panels graded
+ * geometrically towards the foot t* of the perpendicular from r0 to the edge
+ * line (widths sqrt(d^2 + h^2)/|b - a| times powers of 2), where the integrand
+ * varies fastest.  On the plane (hs = 0) M = 0.
+ */
+static void near_edge(const double *a, const double *b, const double *r0, const double *n, double h,
+                      const double *gx, const double *gw, int k, double *iL, double *iM) {
+  double e[3], ar[3], c[3];
+  sub3(b, a, e);
+  sub3(a, r0, ar);
+  cross3(ar, e, c);
+  const double A2 = dot3(c, n);
+  *iL = 0.0;
+  *iM = 0.0;
+  const double L2 = dot3(e, e);
+  if (A2 == 0.0 || L2 == 0.0) return;
+  const double ts = -dot3(ar, e) / L2;
+  /* distance of r0 from the edge line: |A2| = d |b - a| (r0, a, b lie in the
+     plane), consistent with A2 and free of the cancellation of |ar|^2 - (ar.e)^2/L2 */
+  const double d2 = A2 * A2 / L2;
+  const double w0 = sqrt((d2 + h * h) / L2);
+  /* breakpoints: 0, 1 and t* +- w0 2^j inside (0, 1) */
+  double bp[256];
+  int nb = 0;
+  bp[nb++] = 0.0;
+  bp[nb++] = 1.0;
+  if (ts > 0.0 && ts < 1.0) bp[nb++] = ts;
+  for (int j = 0; j < 60 && nb < 250; ++j) {
+    const double w = w0 * ldexp(1.0, j);
+    if (w > 2.0) break;
+    if (ts - w > 0.0 && ts - w < 1.0) bp[nb++] = ts - w;
+    if (ts + w > 0.0 && ts + w < 1.0) bp[nb++] = ts + w;
+  }
+  /* sort (insertion; nb is small) */
+  for (int i = 1; i < nb; ++i) {
+    const double v = bp[i];
+    int j = i - 1;
+    while (j >= 0 && bp[j] > v) {
+      bp[j + 1] = bp[j];
+      --j;
+    }
+    bp[j + 1] = v;
+  }
+  double sL = 0.0, sM = 0.0;
+  for (int i = 0; i + 1 < nb; ++i) {
+    const double t0 = bp[i], t1 = bp[i + 1], dt = t1 - t0;
+    if (!(dt > 0.0)) continue;
+    for (int g = 0; g < k; ++g) {
+      const double t = t0 + dt * gx[g];
+      const double rho2 = d2 + L2 * (t - ts) * (t - ts);
+      const double R = sqrt(rho2 + h * h);
+      sL += dt * gw[g] / (R + h);
+      sM += dt * gw[g] / (R * (R + h));
+    }
+  }
+  *iL = A2 * sL;
+  *iM = A2 * sM;
+}
+
+int orc_near_one(const double *r, const double *x1, const double *x2, const double *x3, int k, double *L,
+                 double *M) {
+  if (k < 1 || k > 4 * ORC_KMAX) return -1;
+  double gx[4 * ORC_KMAX], gw[4 * ORC_KMAX];
+  orc_gauss_legendre01(k, gx, gw);
+  double u[3], v[3], n[3], rx[3];
+  sub3(x2, x1, u);
+  sub3(x3, x1, v);
+  cross3(u, v, n);
+  const double J = sqrt(dot3(n, n));
+  *L = 0.0;
+  *M = 0.0;
+  if (!(J > 0.0)) return 0; /* degenerate: zero area */
+  for (int i = 0; i < 3; ++i) n[i] /= J;
+  sub3(r, x1, rx);
+  const double hs = dot3(rx, n);
+  const double h = fabs(hs);
+  double r0[3];
+  for (int i = 0; i < 3; ++i) r0[i] = r[i] - hs * n[i];
+  const double *xs[4] = {x1, x2, x3, x1};
+  double sL = 0.0, sM = 0.0;
+  for (int q = 0; q < 3; ++q) {
+    double iL, iM;
+    near_edge(xs[q], xs[q + 1], r0, n, h, gx, gw, k, &iL, &iM);
+    sL += iL;
+    sM += iM;
+  }
+  *L = sL / (4.0 * ORC_PI);
+  *M = (hs > 0.0 ? 1.0 : (hs < 0.0 ? -1.0 : 0.0)) * sM / (4.0 * ORC_PI);
+  return 0;
+}
+
+/*
+ * Per pair p in [pair_start[t], pair_start[t+1]) of target t: L and M of
+ * triangle pair_tri[p] at targets[t] (unit density).  Bad triangle or vertex
+ * indices give -1 and leave the pair's outputs 0.  OpenMP over targets.
+ */
+int orc_near(const double *verts, int64_t nv, const int32_t *tris, int64_t ntri, const double *targets, int64_t nt,
+             const int64_t *pair_start, const int32_t *pair_tri, int k, int nthreads, double *out_L, double *out_M) {
+  int err = 0;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+#pragma omp parallel for schedule(dynamic, 16) reduction(min : err)
+  for (int64_t t = 0; t < nt; ++t) {
+    for (int64_t p = pair_start[t]; p < pair_start[t + 1]; ++p) {
+      out_L[p] = 0.0;
+      out_M[p] = 0.0;
+      const int32_t j = pair_tri[p];
+      if (j < 0 || j >= ntri) {
+        err = -1;
+        continue;
+      }
+      const int32_t *tv = &tris[3 * (int64_t)j];
+      if (tv[0] < 0 || tv[0] >= nv || tv[1] < 0 || tv[1] >= nv || tv[2] < 0 || tv[2] >= nv) {
+        err = -1;
+        continue;
+      }
+      orc_near_one(&targets[3 * t], &verts[3 * (int64_t)tv[0]], &verts[3 * (int64_t)tv[1]],
+                   &verts[3 * (int64_t)tv[2]], k, &out_L[p], &out_M[p]);
+    }
+  }
+  return err;
+}

@@ -641,3 +641,175 @@ def test_m2m_identity_composition_and_skips():
     assert np.max(np.abs(two - 2 * d) / (sd + 1e-300)) < 1e-13
     bad, _, skipped = oracle.m2m(p, np.concatenate([F, F]), np.stack([c1, c1]), np.array([0, 5], np.int32), c3[None])
     assert skipped == 1 and np.array_equal(bad, d)
+
+
+# ----------------------------------------------------------------- near field (analytic integrals)
+_NEAR_TRI = np.array([[0.0, 0.0, 0.0], [1.0, 0.1, 0.05], [0.3, 0.9, -0.1]])
+
+
+def _mp_vec(v):
+    import mpmath as mp
+    return [mp.mpf(float(c)) for c in v]
+
+
+def _solid_angle_mp(r, xv):
+    """Signed solid angle of the triangle seen from r, closed form of Van
+    Oosterom & Strackee (IEEE Trans. Biomed. Eng. 30 (1983)), R_i = x_i - r,
+    evaluated with 50 digits on the given (double) inputs."""
+    import mpmath as mp
+    mp.mp.dps = 50
+    rr = _mp_vec(r)
+    R = [[c - d for c, d in zip(_mp_vec(x), rr)] for x in xv]
+    dot = lambda a, b: sum(a[i] * b[i] for i in range(3))  # noqa: E731
+    cross = lambda a, b: [a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]]  # noqa: E731
+    nr = [mp.sqrt(dot(x, x)) for x in R]
+    num = dot(R[0], cross(R[1], R[2]))
+    den = nr[0] * nr[1] * nr[2] + dot(R[0], R[1]) * nr[2] + dot(R[0], R[2]) * nr[1] + dot(R[1], R[2]) * nr[0]
+    return 2 * mp.atan2(num, den)
+
+
+def _contour_L_mp(r, xv):
+    """The contour formula of Sec. 4.1, Eq. (63) for L (no sign choice
+    needed), evaluated with 50 digits on the given (double) inputs."""
+    import mpmath as mp
+    mp.mp.dps = 50
+    X = [_mp_vec(x) for x in xv]
+    rr = _mp_vec(r)
+    sub = lambda a, b: [a[i] - b[i] for i in range(3)]  # noqa: E731
+    dot = lambda a, b: sum(a[i] * b[i] for i in range(3))  # noqa: E731
+    cross = lambda a, b: [a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]]  # noqa: E731
+    nv = cross(sub(X[1], X[0]), sub(X[2], X[0]))
+    nn = mp.sqrt(dot(nv, nv))
+    nv = [c / nn for c in nv]
+    h = abs(dot(sub(rr, X[0]), nv))
+
+    def MP(x, y, z):
+        R = mp.sqrt(x * x + y * y + z * z)
+        den = R * z * z + y * x * x
+        return mp.mpf(0) if den == 0 else -mp.atan(x * z * (R - y) / den)
+
+    def LP(x, y, z):
+        R = mp.sqrt(x * x + y * y + z * z)
+        return -y * MP(x, y, z) - (z * mp.log(abs(R + x)) if z != 0 else 0)
+
+    tot = mp.mpf(0)
+    for q in range(3):
+        e = sub(X[(q + 1) % 3], X[q])
+        lq = mp.sqrt(dot(e, e))
+        iq = [c / lq for c in e]
+        nq = cross(iq, nv)
+        xx = dot(sub(rr, X[q]), iq)
+        zq = dot(sub(rr, X[q]), nq)
+        tot += LP(lq - xx, h, zq) - LP(-xx, h, zq)
+    return tot / (4 * mp.pi)
+
+
+def _dist_to_boundary(r, xv):
+    d = np.inf
+    for q in range(3):
+        a, b = xv[q], xv[(q + 1) % 3]
+        t = np.clip(np.dot(r - a, b - a) / np.dot(b - a, b - a), 0.0, 1.0)
+        d = min(d, np.linalg.norm(r - (a + t * (b - a))))
+    return d
+
+
+def _near_targets(xv, rng, n=40):
+    """Targets above/below the interior, near edges and vertices, at heights
+    from 1e-9 to 3 element sizes (both sides)."""
+    nrm = np.cross(xv[1] - xv[0], xv[2] - xv[0])
+    nrm /= np.linalg.norm(nrm)
+    out = []
+    for _ in range(n):
+        if rng.random() < 0.6:
+            w = rng.dirichlet([1, 1, 1])
+        else:
+            w12 = rng.uniform(-0.5, 1.2, 2)
+            w = np.array([w12[0], w12[1], 1.0 - w12.sum()])
+        base = w @ xv
+        h = 10.0 ** rng.uniform(-9, 0.5) * (1 if rng.random() < 0.5 else -1)
+        out.append(base + h * nrm)
+    for q in range(3):  # just above a vertex and an edge midpoint
+        out.append(xv[q] + 1e-7 * nrm)
+        out.append(0.5 * (xv[q] + xv[(q + 1) % 3]) - 1e-6 * nrm)
+    return out
+
+
+def test_near_far_matches_direct_quadrature():
+    """Away from the triangle plain Gauss quadrature of G and dG/dn converges:
+    the near-field oracle must agree with it (single and double layer)."""
+    rng = np.random.default_rng(21)
+    for _ in range(12):
+        xv = _rand_simplex(3, scale=0.4, rng=rng)
+        r = xv.mean(axis=0) + rng.normal(size=3) * 1.5
+        L, M = oracle.near_one(r, xv)
+        dl = refmath.direct_potential("single", r, list(xv), k=60)
+        dm = refmath.direct_potential("double", r, list(xv), k=60)
+        assert abs(L - dl) <= 1e-13 * abs(dl)
+        assert abs(M - dm) <= 1e-13 * abs(L)  # M is bounded by the single layer's scale here
+
+
+def test_near_double_layer_is_the_solid_angle():
+    """M(r) = -Omega(r)/(4 pi) for a flat triangle (Omega: the closed form of
+    Van Oosterom & Strackee at 50 digits), at heights down to 1e-9 over the
+    interior, the edges and the vertices, on both sides; M = 0 on the plane.
+    Near the boundary M varies like 1/delta with the distance delta to it, so
+    the bar is 1e-14 + 4 eps S / delta (S the coordinate scale): the rounding of
+    the inputs' projections alone moves M by that much."""
+    rng = np.random.default_rng(22)
+    for xv in (_NEAR_TRI, _rand_simplex(3, scale=0.5, rng=rng)):
+        S = float(np.abs(xv).max()) + 1.0
+        for r in _near_targets(xv, rng):
+            _, M = oracle.near_one(r, xv)
+            ref = float(-_solid_angle_mp(r, xv) / (4 * math.pi))
+            tol = 1e-14 + 4 * 2.2e-16 * S / _dist_to_boundary(r, xv)
+            assert abs(M - ref) <= tol, (r, M, ref)
+    # exactly on the plane (a triangle in z = 0, targets with z = 0): M = 0
+    eq = np.array([[0.1, 0.0, 0.0], [0.9, 0.2, 0.0], [0.3, 0.8, 0.0]])
+    for r in (np.array([0.4, 0.3, 0.0]), np.array([2.0, -1.0, 0.0])):
+        assert oracle.near_one(r, eq)[1] == 0.0
+
+
+def test_near_single_layer_closed_forms():
+    """(i) the contour formula of Sec. 4.1, Eq. (63) (its L part) at 50 digits,
+    at near targets on both sides; (ii) the centroid of an equilateral
+    triangle of side a, on its plane: sqrt(3) a ln(2 + sqrt(3)) / (4 pi);
+    (iii) continuity through the plane with the jump -1/2 of the normal
+    derivative: L(h) = L(0) - h/2 + O(h^2 log h) over an interior point, and
+    M -> +-1/2 there."""
+    rng = np.random.default_rng(23)
+    for xv in (_NEAR_TRI, _rand_simplex(3, scale=0.5, rng=rng)):
+        for r in _near_targets(xv, rng):
+            L, _ = oracle.near_one(r, xv)
+            ref = float(_contour_L_mp(r, xv))
+            assert abs(L - ref) <= 5e-14 * abs(ref), (r, L, ref)
+    a = 0.7
+    eq = np.array([[0, 0, 0], [a, 0, 0], [a / 2, a * math.sqrt(3) / 2, 0]])
+    L, M = oracle.near_one(eq.mean(axis=0), eq)
+    assert abs(L - math.sqrt(3) * a * math.log(2 + math.sqrt(3)) / (4 * math.pi)) <= 1e-15 and M == 0.0
+    x0 = 0.25 * _NEAR_TRI[0] + 0.35 * _NEAR_TRI[1] + 0.4 * _NEAR_TRI[2]
+    nrm = np.cross(_NEAR_TRI[1] - _NEAR_TRI[0], _NEAR_TRI[2] - _NEAR_TRI[0])
+    nrm /= np.linalg.norm(nrm)
+    L0, _ = oracle.near_one(x0, _NEAR_TRI)
+    for h in (1e-4, 1e-6):
+        for sgn in (1, -1):
+            Lh, Mh = oracle.near_one(x0 + sgn * h * nrm, _NEAR_TRI)
+            assert abs(Lh - (L0 - h / 2)) <= 20 * h * h * abs(math.log(h)) + 1e-15
+            assert abs(Mh - sgn * 0.5) <= 10 * h  # the solid angle tends to 2 pi from either side
+
+
+def test_near_pairs_csr_and_bad_ids():
+    """The CSR entry point reproduces near_one per pair; bad triangle ids are
+    reported and their entries left 0."""
+    rng = np.random.default_rng(24)
+    verts = rng.normal(size=(12, 3))
+    tris = np.array([[0, 1, 2], [3, 4, 5], [6, 7, 8], [9, 10, 11]], np.int32)
+    targets = rng.normal(size=(3, 3))
+    ps = np.array([0, 2, 2, 5], np.int64)
+    pt = np.array([1, 3, 0, 2, 3], np.int32)
+    L, M = oracle.near(verts, tris, targets, ps, pt)
+    for t in range(3):
+        for p in range(ps[t], ps[t + 1]):
+            l1, m1 = oracle.near_one(targets[t], verts[tris[pt[p]]])
+            assert L[p] == l1 and M[p] == m1
+    with pytest.raises(AssertionError):
+        oracle.near(verts, tris, targets, ps, np.array([1, 3, 0, 9, 3], np.int32))
