@@ -675,7 +675,10 @@ int orc_m2m(int p, int norm, const double *child, const double *child_center, co
  * The t-integrals use Gauss-Legendre (k nodes) on panels graded
  * geometrically towards the foot t* of the perpendicular from r0 to the edge
  * line (widths sqrt(d^2 + h^2)/|b - a| times powers of 2), where the integrand
- * varies fastest.  On the plane (hs = 0) M = 0.
+ * varies fastest.  On the plane M = 0 (the principal value); a target within
+ * 1e-12 times the longest edge of the plane counts as on it, so that
+ * collocation at a point of the element itself (whose computed height is
+ * rounding noise) gets the principal value rather than a one-sided +-1/2.
  */
 static void near_edge(const double *a, const double *b, const double *r0, const double *n, double h,
                       const double *gx, const double *gw, int k, double *iL, double *iM) {
@@ -746,10 +749,20 @@ int orc_near_one(const double *r, const double *x1, const double *x2, const doub
   if (!(J > 0.0)) return 0; /* degenerate: zero area */
   for (int i = 0; i < 3; ++i) n[i] /= J;
   sub3(r, x1, rx);
-  const double hs = dot3(rx, n);
-  const double h = fabs(hs);
+  double hs = dot3(rx, n);
   double r0[3];
   for (int i = 0; i < 3; ++i) r0[i] = r[i] - hs * n[i];
+  /* a target within 1e-12 (longest edge) of the plane is on it: principal
+     value M = 0 and h = 0 (collocation on the element itself) */
+  {
+    double e1[3], e2[3], e3[3];
+    sub3(x2, x1, e1);
+    sub3(x3, x2, e2);
+    sub3(x1, x3, e3);
+    const double lmax = sqrt(fmax(dot3(e1, e1), fmax(dot3(e2, e2), dot3(e3, e3))));
+    if (fabs(hs) <= 1e-12 * lmax) hs = 0.0;
+  }
+  const double h = fabs(hs);
   const double *xs[4] = {x1, x2, x3, x1};
   double sL = 0.0, sM = 0.0;
   for (int q = 0; q < 3; ++q) {

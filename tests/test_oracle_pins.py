@@ -797,6 +797,26 @@ def test_near_single_layer_closed_forms():
             assert abs(Mh - sgn * 0.5) <= 10 * h  # the solid angle tends to 2 pi from either side
 
 
+def test_near_on_element_is_the_principal_value():
+    """Collocation at a point of the element itself (its centroid, whose
+    computed height is rounding noise): M = 0 and L = its value on the plane;
+    a height of 1e-9 (above the 1e-12 on-plane band) gives the one-sided limits
+    M = +-1/2."""
+    a = 0.7
+    eq = np.array([[0, 0, 0], [a, 0, 0], [a / 2, a * math.sqrt(3) / 2, 0]])
+    Rz = np.array([[0.6, -0.8, 0.0], [0.48, 0.36, -0.8], [0.64, 0.48, 0.6]])  # a rotation
+    xv = eq @ Rz.T + np.array([0.3, -0.2, 0.1])
+    c = xv.mean(axis=0)
+    L, M = oracle.near_one(c, xv)
+    assert M == 0.0
+    assert abs(L - math.sqrt(3) * a * math.log(2 + math.sqrt(3)) / (4 * math.pi)) <= 1e-14
+    nrm = np.cross(xv[1] - xv[0], xv[2] - xv[0])
+    nrm /= np.linalg.norm(nrm)
+    for sgn in (1, -1):
+        _, M1 = oracle.near_one(c + sgn * 1e-9 * nrm, xv)
+        assert abs(M1 - sgn * 0.5) <= 1e-8
+
+
 def test_near_pairs_csr_and_bad_ids():
     """The CSR entry point reproduces near_one per pair; bad triangle ids are
     reported and their entries left 0."""
