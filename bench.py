@@ -336,6 +336,49 @@ def upward_pass(dev, reps=20):
     return res
 
 
+def near_field(dev, reps=10):
+    """Near field of the headline sphere at its collocation points: targets at
+    the 81,920 triangle centroids, pairs with every triangle of the 27 boxes
+    around the target's box (q2x_near, closed form, FP64), single + double
+    layer densities; the unit-density entries (stored near-field matrix) and
+    the potentials.  Timed with HIP events."""
+    import torch
+
+    from paper_2107_10942_amd import q2x
+    from q2x_inputs import configs, octree
+    single, double = configs.perturbed_sphere_pair()
+    cen = single.verts[single.elems].mean(axis=1)
+    ps, pe = octree.near_pairs(single.boxes, single.elem_box, single.elem_box)
+    t = lambda a, dt: torch.as_tensor(a, dtype=dt, device=dev).contiguous()  # noqa: E731
+    v, e, c = t(single.verts, torch.float64), t(single.elems, torch.int32), t(cen, torch.float64)
+    pst, pet = t(ps, torch.int64), t(pe, torch.int32)
+    ds, dd = t(single.density, torch.float64), t(double.density, torch.float64)
+    npair = int(pe.shape[0])
+    eL = torch.empty(npair, dtype=torch.float64, device=dev)
+    eM = torch.empty(npair, dtype=torch.float64, device=dev)
+    pot = torch.empty(len(cen), dtype=torch.float64, device=dev)
+    ws = q2x.alloc_near_workspace(dev)
+    stream = torch.cuda.current_stream()
+    res = {"workload": f"perturbed icosphere k=6: {len(cen)} collocation targets (centroids), pairs with the "
+                       f"triangles of the 27 surrounding level-5 boxes", "pairs": npair}
+    for name, kw in (("potentials", dict(entries=False, out_potential=pot)),
+                     ("entries_and_potentials", dict(out_entries=(eL, eM), out_potential=pot))):
+        call = lambda: q2x.near(v, e, c, pst, pet, ds, dd, workspace=ws, stream=stream, **kw)  # noqa: E731
+        for _ in range(2):
+            call()
+        torch.cuda.synchronize()
+        a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            call()
+        z.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(z) / reps
+        res[name] = {"call_ms": ms, "pairs_per_s": npair / (ms * 1e-3)}
+    res["status"] = list(q2x.status(ws))
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -492,6 +535,7 @@ def main():
         line["other_workloads"] = other_workloads(dev)
         line["receiving_side"] = receiving_side(dev)
         line["upward_pass"] = upward_pass(dev)
+        line["near_field"] = near_field(dev)
     if not args.no_batch:
         line["batch_workload"] = batch_workload(dev)
     if not args.no_serving:

@@ -267,6 +267,38 @@ q2x_status q2x_m2m(const double* child_coeffs, const double* child_center, const
                    double* parent_coeffs, void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * Near field: single- and double-layer potentials of flat triangles with
+ * constant density at nearby targets, in closed form (Sec. 4.1, Eq. (63);
+ * the double layer multiplied by sign((r - x1).n), which the printed formula
+ * omits), for (target, triangle) pairs in compressed rows by target:
+ *   L_j(r) = int_Tj G(r, y) dS_y,   M_j(r) = int_Tj dG/dn_y dS_y,   G = 1/(4 pi |r - y|),
+ *   n = (x2 - x1) x (x3 - x1)/|.| on the given vertex order.
+ *   targets     [n_targets][3]
+ *   pair_start  [n_targets + 1] int64: target t's pairs are
+ *               pair_tri[pair_start[t] .. pair_start[t+1]) (triangle indices)
+ *   entries_L/M [n_pairs] out, or NULL: the unit-density values (the stored
+ *               near-field matrix)
+ *   potential   [n_targets] out, or NULL: sum over the target's pairs of
+ *               density_single[j] L_j + density_double[j] M_j (either density
+ *               may be NULL: its term is omitted; at least one is needed);
+ *               Q2X_ACCUMULATE adds to it
+ * A target within 1e-12 times the triangle's longest edge of its plane counts
+ * as on it: M = 0 (the principal value) and L its value on the plane; this
+ * covers collocation on the element itself.  Bad triangle ids and malformed
+ * rows set Q2X_FLAG_BAD_BOX, bad vertex indices Q2X_FLAG_BAD_VERTEX,
+ * non-finite coordinates Q2X_FLAG_NONFINITE; such pairs give 0 and are
+ * counted as skipped; zero-area triangles give 0 and are counted as
+ * degenerate.  FP64.  Workspace: q2x_near_workspace_bytes() bytes (the status
+ * block).
+ */
+size_t q2x_near_workspace_bytes(void);
+q2x_status q2x_near(const double* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris, const double* targets,
+                    int64_t n_targets, const int64_t* pair_start, const int32_t* pair_tri, int64_t n_pairs,
+                    const double* density_single, const double* density_double, double* entries_L,
+                    double* entries_M, double* potential, unsigned flags, void* workspace, size_t workspace_bytes,
+                    void* stream);
+
+/*
  * Batches: many meshes (jobs) in one replayed launch sequence.  A job is one
  * single call's arguments; kind may be any q2x_kind (density2/coeffs2 only for
  * Q2X_TRI_BOTH; for Q2X_SEGMENT_VEC density is [N][3] and coeffs [3][B][..]).  Q2X_PRESORTED is accepted and has no effect (the batch always

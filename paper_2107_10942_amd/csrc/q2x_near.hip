@@ -1,0 +1,262 @@
+// q2x_near.hip -- near field: single- and double-layer potentials of flat
+// triangles with constant density at nearby targets, in closed form (the
+// contour formula of Sec. 4.1, Eq. (63)), for (target, triangle) pairs given
+// in compressed rows by target.  This is the part of an FMM-accelerated BEM
+// step that the multipole expansions do not cover; computed on the fly it is
+// where the time goes (Sec. 4.2).
+//
+// Per pair, for the triangle x1 x2 x3 with unit normal n = (x2-x1)x(x3-x1)/|.|,
+// signed height hs = (r - x1).n and h = |hs|, edges q (x_q -> x_q+1, length
+// l_q, unit direction i_q, in-plane normal n_q = i_q x n):
+//   L(r) = (1/4pi) sum_q [L_P(l_q - x_q, h, z_q) - L_P(-x_q, h, z_q)]
+//   M(r) = sign(hs) (1/4pi) sum_q [M_P(l_q - x_q, h, z_q) - M_P(-x_q, h, z_q)]
+//   x_q = (r - x_q).i_q,  z_q = (r - x_q).n_q,
+//   M_P(x, y, z) = -atan(x z (R - y) / (R z^2 + y x^2)),
+//   L_P(x, y, z) = -y M_P(x, y, z) - z ln(R + x),  R = sqrt(x^2 + y^2 + z^2).
+// The printed M lacks the factor sign(hs): with h = |hs| the contour sum is
+// the value on the +n side, and M is odd in hs.  R - y and R + x (x < 0) are
+// formed without cancellation as (x^2 + z^2)/(R + y) and (y^2 + z^2)/(R - x);
+// terms with z = 0 vanish.  A target within 1e-12 (longest edge) of the plane
+// counts as on it: h = 0 and M = 0, the principal value (collocation on the
+// element itself, whose computed height is rounding noise).
+//
+// One wavefront per target: lanes take the target's pairs in strides of 64,
+// write the per-pair values if asked (the stored near-field matrix) and sum
+// sigma_j L + mu_j M; a butterfly reduction gives the target's potential.
+#include <math.h>
+
+#include "q2x_internal.hpp"
+
+namespace q2x {
+
+struct NearArgs {
+  const double* verts;
+  const int32_t* tris;
+  const double* targets;
+  const int64_t* pair_start;  // [n_targets + 1]
+  const int32_t* pair_tri;    // [n_pairs]
+  const double* dens_single;  // [n_tris] or nullptr
+  const double* dens_double;  // [n_tris] or nullptr
+  double* entries_L;          // [n_pairs] or nullptr
+  double* entries_M;          // [n_pairs] or nullptr
+  double* pot;                // [n_targets] or nullptr
+  Status* status;
+  int64_t n_verts, n_tris, n_targets, n_pairs;
+  int accumulate;
+};
+
+constexpr double kInv4PiNear = 0.07957747154594766788;
+
+__device__ __forceinline__ double near_MP(double x, double y, double z) {
+  if (z == 0.0) return 0.0;
+  const double R = sqrt(x * x + y * y + z * z);
+  const double Rmy = (x * x + z * z) / (R + y);  // R - y, y >= 0
+  const double den = R * z * z + y * x * x;      // > 0 for z != 0
+  return -atan(x * z * Rmy / den);
+}
+
+__device__ __forceinline__ double near_LP(double x, double y, double z, double mp) {
+  if (z == 0.0) return -y * mp;
+  const double R = sqrt(x * x + y * y + z * z);
+  const double Rpx = (x >= 0.0) ? R + x : (y * y + z * z) / (R - x);  // > 0 for z != 0
+  return -y * mp - z * log(Rpx);
+}
+
+// Cross product without contraction into FMAs: parallel edge vectors (a
+// zero-area triangle) give exactly 0.
+__device__ __forceinline__ void near_cross(double ux, double uy, double uz, double vx, double vy, double vz,
+                                          double& cx, double& cy, double& cz) {
+#pragma clang fp contract(off)
+  cx = uy * vz - uz * vy;
+  cy = uz * vx - ux * vz;
+  cz = ux * vy - uy * vx;
+}
+
+// L and M of one unit-density triangle at r; returns false for a degenerate
+// (zero-area) triangle (L = M = 0).
+__device__ bool near_pair(const double* r, const double (&X)[3][3], double& L, double& M) {
+  const double ux = X[1][0] - X[0][0], uy = X[1][1] - X[0][1], uz = X[1][2] - X[0][2];
+  const double vx = X[2][0] - X[0][0], vy = X[2][1] - X[0][1], vz = X[2][2] - X[0][2];
+  double cx, cy, cz;
+  near_cross(ux, uy, uz, vx, vy, vz, cx, cy, cz);
+  const double J = sqrt(cx * cx + cy * cy + cz * cz);
+  L = 0.0;
+  M = 0.0;
+  if (!(J > 0.0)) return false;
+  const double nx = cx / J, ny = cy / J, nz = cz / J;
+  double l2max = 0.0;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int q1 = (q + 1) % 3;
+    const double ex = X[q1][0] - X[q][0], ey = X[q1][1] - X[q][1], ez = X[q1][2] - X[q][2];
+    l2max = fmax(l2max, ex * ex + ey * ey + ez * ez);
+  }
+  double hs = (r[0] - X[0][0]) * nx + (r[1] - X[0][1]) * ny + (r[2] - X[0][2]) * nz;
+  if (fabs(hs) <= 1e-12 * sqrt(l2max)) hs = 0.0;
+  const double h = fabs(hs);
+  double sL = 0.0, sM = 0.0;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int q1 = (q + 1) % 3;
+    const double ex = X[q1][0] - X[q][0], ey = X[q1][1] - X[q][1], ez = X[q1][2] - X[q][2];
+    const double l = sqrt(ex * ex + ey * ey + ez * ez);
+    const double ix = ex / l, iy = ey / l, iz = ez / l;
+    // n_q = i_q x n
+    const double mx = iy * nz - iz * ny, my = iz * nx - ix * nz, mz = ix * ny - iy * nx;
+    const double dx = r[0] - X[q][0], dy = r[1] - X[q][1], dz = r[2] - X[q][2];
+    const double xq = dx * ix + dy * iy + dz * iz;
+    const double zq = dx * mx + dy * my + dz * mz;
+    const double m1 = near_MP(l - xq, h, zq), m0 = near_MP(-xq, h, zq);
+    sM += m1 - m0;
+    sL += near_LP(l - xq, h, zq, m1) - near_LP(-xq, h, zq, m0);
+  }
+  L = sL * kInv4PiNear;
+  M = (hs > 0.0 ? sM : (hs < 0.0 ? -sM : 0.0)) * kInv4PiNear;
+  return true;
+}
+
+__global__ __launch_bounds__(256) void q2x_near_kernel(NearArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  uint32_t flag = 0;
+  unsigned long long ndeg = 0, nskip = 0;
+  for (int64_t t = wave; t < a.n_targets; t += nwaves) {  // uniform per wavefront
+    int64_t s0 = a.pair_start[t], s1 = a.pair_start[t + 1];
+    if (s0 < 0 || s1 > a.n_pairs || s1 < s0) {  // malformed rows: no pairs read
+      flag |= Q2X_FLAG_BAD_BOX;
+      s0 = s1 = 0;
+    }
+    const double r[3] = {a.targets[3 * t], a.targets[3 * t + 1], a.targets[3 * t + 2]};
+    const bool rfin = isfinite(r[0]) && isfinite(r[1]) && isfinite(r[2]);
+    double acc = 0.0;
+    for (int64_t p = s0 + lane; p < s1; p += 64) {
+      double L = 0.0, M = 0.0;
+      const int32_t j = a.pair_tri[p];
+      bool ok = rfin;
+      if (j < 0 || j >= a.n_tris) {
+        ok = false;
+        flag |= Q2X_FLAG_BAD_BOX;
+      }
+      double X[3][3];
+      if (ok) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const int32_t vi = a.tris[3 * (int64_t)j + k];
+          if (vi < 0 || vi >= a.n_verts) {
+            ok = false;
+            flag |= Q2X_FLAG_BAD_VERTEX;
+            X[k][0] = X[k][1] = X[k][2] = 0.0;
+          } else {
+            X[k][0] = a.verts[3 * (int64_t)vi];
+            X[k][1] = a.verts[3 * (int64_t)vi + 1];
+            X[k][2] = a.verts[3 * (int64_t)vi + 2];
+          }
+        }
+      }
+      if (ok) {
+        bool fin = true;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) fin = fin && isfinite(X[k][0]) && isfinite(X[k][1]) && isfinite(X[k][2]);
+        if (!fin) {
+          ok = false;
+          flag |= Q2X_FLAG_NONFINITE;
+        }
+      } else if (!rfin) {
+        flag |= Q2X_FLAG_NONFINITE;
+      }
+      if (ok) {
+        if (!near_pair(r, X, L, M)) ++ndeg;
+        const double ss = a.dens_single ? a.dens_single[j] : 0.0;
+        const double sd = a.dens_double ? a.dens_double[j] : 0.0;
+        acc += ss * L + sd * M;
+      } else {
+        ++nskip;
+      }
+      if (a.entries_L) a.entries_L[p] = L;
+      if (a.entries_M) a.entries_M[p] = M;
+    }
+    // fixed-order butterfly: every lane ends with the same sum
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0 && a.pot) a.pot[t] = a.accumulate ? a.pot[t] + acc : acc;
+  }
+  // status: one atomic per wavefront and counter
+  const uint64_t fl = __ballot(flag != 0);
+  uint32_t fall = 0;
+  if (fl) {
+#pragma unroll
+    for (int b = 0; b < 5; ++b)
+      if (__ballot((flag >> b) & 1u)) fall |= (1u << b);
+  }
+  unsigned long long d = ndeg, s = nskip;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    d += __shfl_xor(d, off);
+    s += __shfl_xor(s, off);
+  }
+  if (lane == 0) {
+    if (d) atomicAdd(&a.status->n_degenerate, d);
+    if (s) atomicAdd(&a.status->n_skipped, s);
+    if (fall) atomicOr(&a.status->flags, fall);
+  }
+}
+
+hipError_t clear_status(Status* st, hipStream_t s);
+
+}  // namespace q2x
+
+using namespace q2x;
+
+extern "C" {
+
+size_t q2x_near_workspace_bytes(void) { return 256; }
+
+q2x_status q2x_near(const double* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris, const double* targets,
+                    int64_t n_targets, const int64_t* pair_start, const int32_t* pair_tri, int64_t n_pairs,
+                    const double* density_single, const double* density_double, double* entries_L,
+                    double* entries_M, double* potential, unsigned flags, void* workspace, size_t workspace_bytes,
+                    void* stream) {
+  if (n_verts < 0 || n_tris < 0 || n_targets < 0 || n_pairs < 0 || n_tris >= ((int64_t)1 << 31) ||
+      n_verts >= ((int64_t)1 << 31))
+    return Q2X_ERR_ARG;
+  if (flags & ~(unsigned)Q2X_ACCUMULATE) return Q2X_ERR_ARG;
+  if (!workspace || ((uintptr_t)workspace % 256) != 0) return Q2X_ERR_WORKSPACE;
+  if (workspace_bytes < q2x_near_workspace_bytes()) return Q2X_ERR_WORKSPACE;
+  if (n_targets > 0 && (!targets || !pair_start)) return Q2X_ERR_ARG;
+  if (n_pairs > 0 && (!pair_tri || !verts || !tris)) return Q2X_ERR_ARG;
+  if (potential && !density_single && !density_double) return Q2X_ERR_ARG;  // nothing to sum
+  if (!potential && !entries_L && !entries_M) return Q2X_ERR_ARG;           // nothing to write
+  if (((uintptr_t)verts % 8) || ((uintptr_t)tris % 4) || ((uintptr_t)targets % 8) || ((uintptr_t)pair_start % 8) ||
+      ((uintptr_t)pair_tri % 4) || ((uintptr_t)density_single % 8) || ((uintptr_t)density_double % 8) ||
+      ((uintptr_t)entries_L % 8) || ((uintptr_t)entries_M % 8) || ((uintptr_t)potential % 8))
+    return Q2X_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  Status* st = (Status*)workspace;
+  if (clear_status(st, s) != hipSuccess) return Q2X_ERR_HIP;
+  if (n_targets == 0) return Q2X_OK;
+  NearArgs a{};
+  a.verts = verts;
+  a.tris = tris;
+  a.targets = targets;
+  a.pair_start = pair_start;
+  a.pair_tri = pair_tri;
+  a.dens_single = density_single;
+  a.dens_double = density_double;
+  a.entries_L = entries_L;
+  a.entries_M = entries_M;
+  a.pot = potential;
+  a.status = st;
+  a.n_verts = n_verts;
+  a.n_tris = n_tris;
+  a.n_targets = n_targets;
+  a.n_pairs = n_pairs;
+  a.accumulate = (flags & Q2X_ACCUMULATE) ? 1 : 0;
+  int64_t blocks = (n_targets + 3) / 4;  // four wavefronts per block
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(q2x_near_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a);
+  if (hipGetLastError() != hipSuccess) return Q2X_ERR_HIP;
+  return Q2X_OK;
+}
+
+}  // extern "C"

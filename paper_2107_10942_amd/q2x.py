@@ -28,7 +28,8 @@ EXPORTS = ("q2x_workspace_bytes", "q2x_bucket_workspace_bytes", "q2x_bucket", "q
            "q2x_tri_both", "q2x_segment_vec", "q2x_status_get", "q2x_status_string", "q2x_profile_enable", "q2x_profile_reset",
            "q2x_profile_read", "q2x_version", "q2x_batch_plan", "q2x_batch_workspace_bytes", "q2x_batch_run", "q2x_batch_launch",
            "q2x_batch_job_status", "q2x_batch_groups", "q2x_batch_mode", "q2x_batch_destroy",
-           "q2x_eval_workspace_bytes", "q2x_eval", "q2x_m2m_workspace_bytes", "q2x_m2m")
+           "q2x_eval_workspace_bytes", "q2x_eval", "q2x_m2m_workspace_bytes", "q2x_m2m",
+           "q2x_near_workspace_bytes", "q2x_near")
 
 
 class Q2XError(RuntimeError):
@@ -107,6 +108,10 @@ def lib():
         L.q2x_m2m_workspace_bytes.restype = sz
         L.q2x_m2m.argtypes = [vp, vp, vp, i64, vp, i64, ci, ci, cu, vp, vp, sz, vp]
         L.q2x_m2m.restype = ci
+        L.q2x_near_workspace_bytes.argtypes = []
+        L.q2x_near_workspace_bytes.restype = sz
+        L.q2x_near.argtypes = [vp, i64, vp, i64, vp, i64, vp, vp, i64, vp, vp, vp, vp, vp, cu, vp, sz, vp]
+        L.q2x_near.restype = ci
         _lib = L
     return _lib
 
@@ -428,6 +433,42 @@ def upward(leaf, centers, parents, p, norm=NORM_FMM, stream=None):
     for i, par in enumerate(parents):
         out.append(m2m(out[-1], centers[i], par, centers[i + 1], p, norm=norm, presorted=True, stream=stream))
     return out
+
+
+def alloc_near_workspace(device=None):
+    nbytes = int(lib().q2x_near_workspace_bytes())
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device or "cuda")
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + nbytes]
+
+
+def near(verts, tris, targets, pair_start, pair_tri, density_single=None, density_double=None, entries=True,
+         potential=True, accumulate=False, out_entries=None, out_potential=None, workspace=None, stream=None):
+    """Near-field potentials of triangles at targets (q2x_near), pairs in CSR by
+    target.  Returns (entries_L [P], entries_M [P]) or None, and potential [T] or None."""
+    nt = int(targets.shape[0])
+    npair = int(pair_tri.shape[0])
+    if tuple(pair_start.shape) != (nt + 1,):
+        raise Q2XError(f"pair_start must have shape {(nt + 1,)}")
+    dev = targets.device
+    eL = eM = pot = None
+    if entries:
+        eL, eM = out_entries if out_entries is not None else (
+            torch.empty(npair, dtype=torch.float64, device=dev), torch.empty(npair, dtype=torch.float64, device=dev))
+    if potential:
+        pot = out_potential if out_potential is not None else torch.empty(nt, dtype=torch.float64, device=dev)
+    if workspace is None:
+        workspace = alloc_near_workspace(dev)
+    rc = lib().q2x_near(_ptr(verts, torch.float64, "verts"), int(verts.shape[0]), _ptr(tris, torch.int32, "tris"),
+                        int(tris.shape[0]), _ptr(targets, torch.float64, "targets"), nt,
+                        _ptr(pair_start, torch.int64, "pair_start"), _ptr(pair_tri, torch.int32, "pair_tri"), npair,
+                        _ptr(density_single, torch.float64, "density_single"),
+                        _ptr(density_double, torch.float64, "density_double"),
+                        _ptr(eL, torch.float64, "entries_L"), _ptr(eM, torch.float64, "entries_M"),
+                        _ptr(pot, torch.float64, "potential"), ACCUMULATE if accumulate else 0,
+                        ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream(stream))
+    _check(rc)
+    return ((eL, eM) if entries else None), pot
 
 
 def bucket(elem_box, n_boxes, stream=None, workspace=None):

@@ -108,3 +108,37 @@ def tree_levels(boxes: Boxes, top: int = 2):
         levels.append((ucode, box_centers(ucode, lev, boxes.lo, boxes.half)))
         code = ucode
     return levels, parents
+
+
+def near_pairs(boxes: Boxes, elems_box, target_box):
+    """Near-field pairs: every target with every element of the 27 boxes
+    around (and including) its own box (same level), in compressed rows.
+    elems_box [N] is the box of each element, target_box [T] the box of each
+    target.  Returns (pair_start [T+1] int64, pair_elem [P] int32); within a row
+    the elements are grouped by box in Morton order, increasing index inside a box."""
+    nb = boxes.n_boxes
+    ijk = np.rint((boxes.center - boxes.lo) / boxes.h - 0.5).astype(np.int64)
+    nside = 1 << boxes.level
+    code = boxes.morton
+    order = np.argsort(elems_box, kind="stable")
+    counts = np.bincount(elems_box, minlength=nb)
+    start = np.concatenate([[0], np.cumsum(counts)])
+    # neighbour lists per box (occupied neighbours only, Morton order)
+    offs = np.array([(dx, dy, dz) for dx in (-1, 0, 1) for dy in (-1, 0, 1) for dz in (-1, 0, 1)])
+    nbr = ijk[:, None, :] + offs[None, :, :]
+    valid = np.all((nbr >= 0) & (nbr < nside), axis=2)
+    nbr = np.clip(nbr, 0, nside - 1)
+    ncode = morton3(nbr[..., 0].ravel(), nbr[..., 1].ravel(), nbr[..., 2].ravel()).reshape(nb, 27)
+    pos = np.searchsorted(code, ncode)
+    pos = np.clip(pos, 0, nb - 1)
+    hit = valid & (code[pos] == ncode)
+    box_rows = []
+    for b in range(nb):
+        nbs = np.sort(pos[b][hit[b]])
+        box_rows.append(np.concatenate([order[start[k]:start[k + 1]] for k in nbs]).astype(np.int32))
+    row_len = np.array([len(r) for r in box_rows], dtype=np.int64)
+    tl = row_len[target_box]
+    pair_start = np.concatenate([[0], np.cumsum(tl)]).astype(np.int64)
+    pair_elem = np.concatenate([box_rows[b] for b in target_box]).astype(np.int32) if len(target_box) else \
+        np.zeros(0, np.int32)
+    return pair_start, pair_elem

@@ -128,3 +128,38 @@ def test_eval_argument_errors():
     assert call(local=None) == -1 and call(out=None) == -1
     assert call(wsb=16) == -3 and call(wsp=vp(264)) == -3 and call(wsp=None) == -3
     assert call(out=vp(12)) == -1  # misaligned output
+
+
+def test_near_and_m2m_argument_errors():
+    """q2x_near and q2x_m2m refuse bad arguments synchronously (no device work)."""
+    _ensure_built()
+    from paper_2107_10942_amd import q2x
+    L = q2x.lib()
+    vp = ctypes.c_void_p
+    ws = vp(256)
+    nb = q2x.lib().q2x_near_workspace_bytes()
+    assert nb >= 64
+
+    def near(nv=3, nt=1, ntar=1, npair=1, ds=vp(8), dd=None, eL=vp(8), eM=None, pot=vp(8), flags=0, w=ws, wb=nb,
+             targets=vp(8), ps=vp(8), pt=vp(4)):
+        return L.q2x_near(vp(8), nv, vp(4), nt, targets, ntar, ps, pt, npair, ds, dd, eL, eM, pot, flags, w, wb, None)
+
+    assert near(nv=-1) == -1 and near(npair=-1) == -1
+    assert near(flags=2) == -1  # PRESORTED has no meaning here
+    assert near(ds=None, dd=None) == -1  # a potential needs a density
+    assert near(eL=None, eM=None, pot=None) == -1  # nothing to write
+    assert near(targets=None) == -1 and near(pt=None) == -1
+    assert near(w=None) == -3 and near(w=vp(260)) == -3 and near(wb=8) == -3
+    assert near(pot=vp(12)) == -1  # misaligned
+
+    mb = q2x.lib().q2x_m2m_workspace_bytes(10, 3)
+    assert mb > 0 and q2x.lib().q2x_m2m_workspace_bytes(-1, 3) == 0
+
+    def m2m(p=8, norm=0, flags=0, child=vp(8), out=vp(1 << 20), w=ws, wb=mb, nc=10, npar=3):
+        return L.q2x_m2m(child, vp(8), vp(4), nc, vp(8), npar, p, norm, flags, out, w, wb, None)
+
+    assert m2m(p=33) == -2 and m2m(norm=2) == -1 and m2m(flags=8) == -1
+    assert m2m(child=None) == -1 and m2m(out=None) == -1
+    assert m2m(wb=16) == -3 and m2m(w=None) == -3
+    # parents written over the children being read
+    assert m2m(child=vp(4096), out=vp(4096 + 16 * 81)) == -1
