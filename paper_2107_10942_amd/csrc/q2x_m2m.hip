@@ -16,22 +16,21 @@
 // translation: the kernel reads orders m >= 0 only, computes outputs m >= 0
 // and writes m < 0 from the symmetry.
 //
-// One workgroup of 256 threads per parent.  For each child (the children of
-// a parent are a contiguous run of the box-sorted order): the child's m >= 0
-// coefficients go to LDS, and R_j^q(d) (q >= 0) of the shift d is built in LDS
-// degree by degree with the ladder recursion of the vertex harmonic (Sec. 3.4,
-// Eq. (50): G_j = D G_{j-1}, G_0 = 1, R_j^q = (-i)^q G_j^q / j!).  Thread t
-// then owns outputs (n, m) with tri index t, t + 256, t + 512 and adds
-// sum_{k<=n} sum_l A_k^l R_{n-k}^{+-(l-m)} in FP64 registers.
+// One workgroup per parent, NW wavefronts; wavefront w takes the parent's
+// children w, w + NW, ... (the children of a parent are a contiguous run of
+// the parent-sorted order).  Per child the wavefront builds, in its own LDS
+// region, the child's expansion for all orders (m < 0 from the symmetry) and
+// R_j^q(d) of the shift for all orders: the m >= 0 part by the ladder
+// recursion of the vertex harmonic (Sec. 3.4, Eq. (50): G_j = D G_{j-1},
+// G_0 = 1, R_j^q = (-i)^q G_j^q / j!), then q < 0 from Eq. (12).  Lane l owns
+// the outputs (n, m >= 0) with triangular index l, 127 - l, 128 + l, ... and adds
+// sum_{k<=n} sum_l A_k^l R_{n-k}^{+-(l-m)}: two contiguous LDS streams per
+// degree k.  The wavefronts' partial sums meet in LDS in a fixed order.
 #include <math.h>
 
 #include "q2x_internal.hpp"
 
 namespace q2x {
-
-constexpr int kM2MThreads = 256;
-constexpr int kM2MMaxTri = tri(Q2X_P_MAX + 1);              // 561 coefficients with m >= 0
-constexpr int kM2MPerThread = (kM2MMaxTri + kM2MThreads - 1) / kM2MThreads;  // 3
 
 __device__ __forceinline__ int tri_degree(int o) {
   int n = (int)((sqrt(8.0 * o + 1.0) - 1.0) * 0.5);
@@ -40,17 +39,36 @@ __device__ __forceinline__ int tri_degree(int o) {
   return n;
 }
 
-__global__ __launch_bounds__(kM2MThreads) void q2x_m2m_kernel(M2MArgs a) {
-  __shared__ double sAr[kM2MMaxTri], sAi[kM2MMaxTri];  // child coefficients, m >= 0
-  __shared__ double sRr[kM2MMaxTri], sRi[kM2MMaxTri];  // G_j^q of the shift, then R_j^q
-  __shared__ int s_skip;
-  const int t = threadIdx.x;
+__device__ __forceinline__ int sq_degree(int idx) {  // n with n^2 <= idx < (n+1)^2
+  int n = (int)sqrt((double)idx);
+  while ((n + 1) * (n + 1) <= idx) ++n;
+  while (n * n > idx) --n;
+  return n;
+}
+
+// wave-scope ordering of this wavefront's LDS writes before its later reads
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <int P, int NW>
+__global__ __launch_bounds__(64 * NW) void q2x_m2m_kernel(M2MArgs a) {
+  constexpr int NC = (P + 1) * (P + 1);
+  constexpr int NT = tri(P + 1);
+  constexpr int PER = (NT + 63) / 64;  // outputs per lane
+  __shared__ double2 sbuf[NW][2][NC];  // per wavefront: A (all orders), R (all orders)
+  __shared__ unsigned s_skip[NW];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  double2* const A = sbuf[w][0];
+  double2* const R = sbuf[w][1];
   const int p = a.p;
+  const int ncoef = (p + 1) * (p + 1);
   const int ntri = tri(p + 1);
-  const int64_t ncoef = (int64_t)(p + 1) * (p + 1);
   const bool moment = (a.norm == Q2X_NORM_MOMENT);
 
-  if (blockIdx.x == 0 && t == 0 && a.presorted_bad) {
+  if (blockIdx.x == 0 && threadIdx.x == 0 && a.presorted_bad) {
     // presorted input: ids below 0 sort first, ids >= n_parent last
     const int64_t bad = (int64_t)a.box_start[0] + (a.n_child - (int64_t)a.box_start[a.n_parent]);
     if (bad > 0) {
@@ -59,147 +77,155 @@ __global__ __launch_bounds__(kM2MThreads) void q2x_m2m_kernel(M2MArgs a) {
     }
   }
 
-  for (int64_t b = blockIdx.x; b < a.n_parent; b += gridDim.x) {
-    int no[kM2MPerThread], mo[kM2MPerThread];
-    double accr[kM2MPerThread], acci[kM2MPerThread];
+  // serpentine assignment (lane, 127 - lane, 128 + lane, ...): the work of an
+  // output grows with its degree, so every lane gets a similar total
+  auto out_index = [&](int r) { return 64 * r + ((r & 1) ? 63 - lane : lane); };
+  int no[PER], mo[PER];
 #pragma unroll
-    for (int r = 0; r < kM2MPerThread; ++r) {
-      const int o = t + r * kM2MThreads;
-      no[r] = (o < ntri) ? tri_degree(o) : -1;
-      mo[r] = (o < ntri) ? o - tri(no[r]) : 0;
-      accr[r] = 0.0;
-      acci[r] = 0.0;
-    }
+  for (int r = 0; r < PER; ++r) {
+    const int o = out_index(r);
+    no[r] = (o < ntri) ? tri_degree(o) : -1;
+    mo[r] = (o < ntri) ? o - tri(no[r]) : 0;
+  }
+
+  for (int64_t b = blockIdx.x; b < a.n_parent; b += gridDim.x) {
+    double accr[PER], acci[PER];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) accr[r] = acci[r] = 0.0;
     const double pcx = a.parent_center[3 * b], pcy = a.parent_center[3 * b + 1], pcz = a.parent_center[3 * b + 2];
     const bool pfin = isfinite(pcx) && isfinite(pcy) && isfinite(pcz);
     const int64_t s0 = a.box_start[b], s1 = a.box_start[b + 1];
-    if (t == 0) s_skip = 0;
-    for (int64_t s = s0; s < s1; ++s) {
+    unsigned skipped = 0;
+    for (int64_t s = s0 + w; s < s1; s += NW) {  // uniform per wavefront
       const int64_t c = a.perm ? (int64_t)a.perm[s] : s;
       const double ccx = a.child_center[3 * c], ccy = a.child_center[3 * c + 1], ccz = a.child_center[3 * c + 2];
-      const bool ok = pfin && isfinite(ccx) && isfinite(ccy) && isfinite(ccz);  // uniform
-      if (!ok) {
-        if (t == 0) ++s_skip;
+      if (!(pfin && isfinite(ccx) && isfinite(ccy) && isfinite(ccz))) {
+        ++skipped;
         continue;
       }
       // shift d: FMM c_p - c_c, MOMENT c_c - c_p
       const double sg = moment ? 1.0 : -1.0;
       const double dx = sg * (ccx - pcx), dy = sg * (ccy - pcy), dz = sg * (ccz - pcz);
-      const double* in = a.child + (size_t)c * ncoef * 2;
-      __syncthreads();  // previous child's LDS reads are done
-      for (int o = t; o < ntri; o += kM2MThreads) {
-        const int n = tri_degree(o), m = o - tri(n);
-        const int64_t g = (int64_t)n * n + n + m;
-        sAr[o] = in[2 * g];
-        sAi[o] = in[2 * g + 1];
-      }
-      // ladder: degree j from degree j - 1 (thread q computes order q)
-      const double xr = 0.5 * dx, xi = 0.5 * dy;  // xi = (d_x + i d_y)/2, eta = conj(xi)
-      if (t == 0) {
-        sRr[0] = 1.0;
-        sRi[0] = 0.0;
-      }
-      for (int j = 1; j <= p; ++j) {
-        __syncthreads();
-        double vr = 0.0, vi = 0.0;
-        const int q = t;
-        if (q <= j) {
-          const int b0 = tri(j - 1);
-          auto F = [&](int k, double& fr, double& fi) {
-            if (k < 0 || k > j - 1) {
-              fr = fi = 0.0;
-            } else {
-              fr = sRr[b0 + k];
-              fi = sRi[b0 + k];
-            }
-          };
-          double ar, ai, br, bi, cr, ci;
-          if (q == 0) {
-            // 2 Re(eta F^1) - z F^0
-            F(1, br, bi);
-            F(0, cr, ci);
-            vr = 2.0 * (xr * br + xi * bi) - dz * cr;
-            vi = 0.0;
-          } else {
-            F(q - 1, ar, ai);
-            F(q + 1, br, bi);
-            F(q, cr, ci);
-            // -xi F^{q-1} + eta F^{q+1} - z F^q
-            vr = -(xr * ar - xi * ai) + (xr * br + xi * bi) - dz * cr;
-            vi = -(xr * ai + xi * ar) + (xr * bi - xi * br) - dz * ci;
+      const double* in = a.child + (size_t)c * (size_t)ncoef * 2;
+      wave_sync();  // this wavefront's reads of the previous child are done
+      // the child's expansion, all orders: A^{-m} = (-1)^m conj(A^m)
+      for (int idx = lane; idx < ncoef; idx += 64) {
+        const int n = sq_degree(idx), m = idx - n * n - n;
+        const int am = m < 0 ? -m : m;
+        const int g = n * n + n + am;
+        double re = in[2 * g], im = in[2 * g + 1];
+        if (m < 0) {
+          im = -im;
+          if (am & 1) {
+            re = -re;
+            im = -im;
           }
         }
-        __syncthreads();
-        if (q <= j) {
-          sRr[tri(j) + q] = vr;
-          sRi[tri(j) + q] = vi;
-        }
+        A[idx] = make_double2(re, im);
       }
-      __syncthreads();
-      // R_j^q = (-i)^q G_j^q / j!
-      for (int o = t; o < ntri; o += kM2MThreads) {
+      // G_j^q (q >= 0) of the shift at R[j^2 + j + q], degree by degree
+      const double xr = 0.5 * dx, xi = 0.5 * dy;  // xi = (d_x + i d_y)/2, eta = conj(xi)
+      if (lane == 0) R[0] = make_double2(1.0, 0.0);
+      for (int j = 1; j <= p; ++j) {
+        wave_sync();
+        const int q = lane;
+        const int b0 = (j - 1) * (j - 1) + (j - 1);
+        double vr = 0.0, vi = 0.0;
+        if (q <= j) {
+          auto F = [&](int k) -> double2 { return (k >= 0 && k <= j - 1) ? R[b0 + k] : make_double2(0.0, 0.0); };
+          const double2 f1 = F(q + 1), f0 = F(q);
+          if (q == 0) {  // 2 Re(eta F^1) - z F^0
+            vr = 2.0 * (xr * f1.x + xi * f1.y) - dz * f0.x;
+          } else {  // -xi F^{q-1} + eta F^{q+1} - z F^q
+            const double2 fm = F(q - 1);
+            vr = -(xr * fm.x - xi * fm.y) + (xr * f1.x + xi * f1.y) - dz * f0.x;
+            vi = -(xr * fm.y + xi * fm.x) + (xr * f1.y - xi * f1.x) - dz * f0.y;
+          }
+        }
+        wave_sync();
+        if (q <= j) R[j * j + j + q] = make_double2(vr, vi);
+      }
+      wave_sync();
+      // R_j^q = (-i)^q G_j^q / j!  (q >= 0, in place; one lane per entry)
+      for (int o = lane; o < ntri; o += 64) {
         const int j = tri_degree(o), q = o - tri(j);
         double f = 1.0;
         for (int i = 2; i <= j; ++i) f *= (double)i;
-        const double gr = sRr[o] / f, gi = sRi[o] / f;
+        const double2 g = R[j * j + j + q];
+        const double gr = g.x / f, gi = g.y / f;
         double rr, ri;
-        switch (q & 3) {  // (-i)^q
+        switch (q & 3) {
           case 0: rr = gr; ri = gi; break;
           case 1: rr = gi; ri = -gr; break;
           case 2: rr = -gr; ri = -gi; break;
           default: rr = -gi; ri = gr; break;
         }
-        sRr[o] = rr;
-        sRi[o] = ri;
+        R[j * j + j + q] = make_double2(rr, ri);
       }
-      __syncthreads();
+      wave_sync();
+      // q < 0: R^{-q} = (-1)^q conj(R^q)
+      for (int o = lane; o < ntri; o += 64) {
+        const int j = tri_degree(o), q = o - tri(j);
+        if (q == 0) continue;
+        const double2 v = R[j * j + j + q];
+        const double sgn = (q & 1) ? -1.0 : 1.0;
+        R[j * j + j - q] = make_double2(sgn * v.x, -sgn * v.y);
+      }
+      wave_sync();
       // out_n^m += sum_{k<=n} sum_l A_k^l R_{n-k}^{qq}, qq = l - m (FMM) or m - l (MOMENT)
 #pragma unroll
-      for (int r = 0; r < kM2MPerThread; ++r) {
+      for (int r = 0; r < PER; ++r) {
         const int n = no[r], m = mo[r];
-        if (n < 0) continue;
-        double sr = 0.0, si = 0.0;
+        if (n < 0 || n > p) continue;
+        double sr[4] = {0.0, 0.0, 0.0, 0.0}, si[4] = {0.0, 0.0, 0.0, 0.0};
+        auto mac = [&](int u, const double2 av, const double2 rv) {
+          sr[u] = fma(av.x, rv.x, sr[u]);
+          sr[u] = fma(-av.y, rv.y, sr[u]);
+          si[u] = fma(av.x, rv.y, si[u]);
+          si[u] = fma(av.y, rv.x, si[u]);
+        };
         for (int k = 0; k <= n; ++k) {
           const int j = n - k;
           const int lo = max(-k, m - j), hi = min(k, m + j);
-          const int tk = tri(k), tj = tri(j);
-          for (int l = lo; l <= hi; ++l) {
-            const int al = l < 0 ? -l : l;
-            double ar = sAr[tk + al], ai = sAi[tk + al];
-            if (l < 0) {  // A^{-|l|} = (-1)^l conj(A^{|l|})
-              ai = -ai;
-              if (al & 1) {
-                ar = -ar;
-                ai = -ai;
-              }
-            }
-            const int qq = moment ? (m - l) : (l - m);
-            const int aq = qq < 0 ? -qq : qq;
-            double rr = sRr[tj + aq], ri = sRi[tj + aq];
-            if (qq < 0) {
-              ri = -ri;
-              if (aq & 1) {
-                rr = -rr;
-                ri = -ri;
-              }
-            }
-            sr = fma(ar, rr, sr);
-            sr = fma(-ai, ri, sr);
-            si = fma(ar, ri, si);
-            si = fma(ai, rr, si);
+          const double2* pa = A + k * k + k;
+          const double2* pr = R + j * j + j;
+          const int step = moment ? -1 : 1;
+          int qq = moment ? (m - lo) : (lo - m);
+          int l = lo;
+          for (; l + 3 <= hi; l += 4, qq += 4 * step) {  // four independent chains
+            const double2 a0 = pa[l], a1 = pa[l + 1], a2 = pa[l + 2], a3 = pa[l + 3];
+            const double2 r0 = pr[qq], r1 = pr[qq + step], r2 = pr[qq + 2 * step], r3 = pr[qq + 3 * step];
+            mac(0, a0, r0);
+            mac(1, a1, r1);
+            mac(2, a2, r2);
+            mac(3, a3, r3);
           }
+          for (; l <= hi; ++l, qq += step) mac(0, pa[l], pr[qq]);
         }
-        accr[r] += sr;
-        acci[r] += si;
+        accr[r] += (sr[0] + sr[1]) + (sr[2] + sr[3]);
+        acci[r] += (si[0] + si[1]) + (si[2] + si[3]);
       }
     }
-    // write +m and -m = (-1)^m conj(+m); m = 0 is real
-    double* out = a.out + (size_t)b * ncoef * 2;
+    if (lane == 0) s_skip[w] = skipped;
+    __syncthreads();  // every wavefront is done with its A and R
+    // partial sums of the wavefronts -> LDS (A region of wavefront w)
 #pragma unroll
-    for (int r = 0; r < kM2MPerThread; ++r) {
-      const int n = no[r], m = mo[r];
-      if (n < 0) continue;
-      double vr = accr[r], vi = (m == 0) ? 0.0 : acci[r];
+    for (int r = 0; r < PER; ++r) {
+      const int o = out_index(r);
+      if (o < ntri) sbuf[w][0][o] = make_double2(accr[r], acci[r]);
+    }
+    __syncthreads();
+    // fixed-order sum over the wavefronts, write +m and -m = (-1)^m conj(+m)
+    double* out = a.out + (size_t)b * (size_t)ncoef * 2;
+    for (int o = threadIdx.x; o < ntri; o += 64 * NW) {
+      const int n = tri_degree(o), m = o - tri(n);
+      double vr = 0.0, vi = 0.0;
+#pragma unroll
+      for (int ww = 0; ww < NW; ++ww) {
+        vr += sbuf[ww][0][o].x;
+        vi += sbuf[ww][0][o].y;
+      }
+      if (m == 0) vi = 0.0;
       const int64_t gp = (int64_t)n * n + n + m, gm = (int64_t)n * n + n - m;
       const double sgn = (m & 1) ? -1.0 : 1.0;
       double wr = sgn * vr, wi = -sgn * vi;
@@ -218,11 +244,16 @@ __global__ __launch_bounds__(kM2MThreads) void q2x_m2m_kernel(M2MArgs a) {
         out[2 * gm + 1] = wi;
       }
     }
-    __syncthreads();
-    if (t == 0 && s_skip > 0) {
-      atomicAdd(&a.status->n_skipped, (unsigned long long)s_skip);
-      atomicOr(&a.status->flags, (uint32_t)Q2X_FLAG_NONFINITE);
+    if (threadIdx.x == 0) {
+      unsigned sk = 0;
+#pragma unroll
+      for (int ww = 0; ww < NW; ++ww) sk += s_skip[ww];
+      if (sk) {
+        atomicAdd(&a.status->n_skipped, (unsigned long long)sk);
+        atomicOr(&a.status->flags, (uint32_t)Q2X_FLAG_NONFINITE);
+      }
     }
+    __syncthreads();  // before the next parent reuses the LDS
   }
 }
 
@@ -230,7 +261,24 @@ hipError_t launch_m2m(const M2MArgs& a, hipStream_t s) {
   int64_t blocks = a.n_parent;
   if (blocks > 65536) blocks = 65536;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(q2x_m2m_kernel, dim3((unsigned)blocks), dim3(kM2MThreads), 0, s, a);
+  const int P = bucket_order(a.p);
+  switch (P) {
+#define Q2X_M2M_CASE(PP, NWV)                                                                           \
+  case PP:                                                                                               \
+    hipLaunchKernelGGL((q2x_m2m_kernel<PP, NWV>), dim3((unsigned)blocks), dim3(64 * NWV), 0, s, a); \
+    break;
+    Q2X_M2M_CASE(4, 4)
+    Q2X_M2M_CASE(8, 4)
+    Q2X_M2M_CASE(12, 4)
+    Q2X_M2M_CASE(16, 4)
+    Q2X_M2M_CASE(20, 4)
+    Q2X_M2M_CASE(24, 2)
+    Q2X_M2M_CASE(28, 2)
+    Q2X_M2M_CASE(32, 2)
+#undef Q2X_M2M_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
