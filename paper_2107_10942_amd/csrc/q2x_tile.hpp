@@ -357,14 +357,17 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
   constexpr int NOUT = KI::nout;
   constexpr int CMAX = PrecInfo<T>::cmax;  // coefficients per chunk (<= 32: lanes c and c + 32)
   static_assert(CMAX <= 32, "one lane pair per chunk coefficient");
-  constexpr int SSTR = kTile + 1;  // padded row stride (elements) of the stage
+  // padded row stride (elements) of the stage: SSTR sizeof(T) = 16 (mod 128),
+  // so rows start 16-byte aligned and the 16-byte reads of eight lanes (eight
+  // rows) cover the 32 banks once
+  constexpr int SSTR = (sizeof(T) == 4) ? kTile + 4 : kTile + 2;
   constexpr int NCT = tri(P + 1);
   constexpr bool SCALED = PrecInfo<T>::scaled;
   using Plan = ChunkPlan<P, CMAX, NOUT>;
 
   // stage: weighted value of chunk coefficient c of every element, real part
   // in row c, imaginary part in row CMAX + c
-  __shared__ T stage[2 * CMAX * SSTR];
+  __shared__ __align__(16) T stage[2 * CMAX * SSTR];
   // FP32 path: scale exponents of every box segment of the tile (row 0: the
   // element scales a_e, row 1 + o: the weights s_e of output o)
   __shared__ int sexp[SCALED ? (NOUT + 1) * kTile : 1];
@@ -626,20 +629,36 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
       }
     };
     const T* pv = stage + ((h ? CMAX : 0) + (act ? c : 0)) * SSTR;
+    // BATCH consecutive staged values of the lane's row in 16-byte reads
+    auto load_batch = [&](int off, T (&dst)[BATCH]) Q2X_INLINE {
+      if constexpr (sizeof(T) == 4) {
+        const float4* q = reinterpret_cast<const float4*>(pv + off);
+        static_for<0, BATCH / 4>([&](auto II) Q2X_INLINE {
+          constexpr int i = decltype(II)::value;
+          const float4 v = q[i];
+          dst[4 * i] = v.x;
+          dst[4 * i + 1] = v.y;
+          dst[4 * i + 2] = v.z;
+          dst[4 * i + 3] = v.w;
+        });
+      } else {
+        const double2* q = reinterpret_cast<const double2*>(pv + off);
+        static_for<0, BATCH / 2>([&](auto II) Q2X_INLINE {
+          constexpr int i = decltype(II)::value;
+          const double2 v = q[i];
+          dst[2 * i] = v.x;
+          dst[2 * i + 1] = v.y;
+        });
+      }
+    };
     double a0 = 0.0, a1 = 0.0;  // sums over even / odd positions of the open segment
     T cur[BATCH];
-    static_for<0, BATCH>([&](auto JB) Q2X_INLINE {
-      constexpr int j = decltype(JB)::value;
-      cur[j] = pv[j];
-    });
+    load_batch(0, cur);
 #pragma unroll 1
     for (int b0 = 0; b0 < kTile; b0 += BATCH) {  // uniform
       T nxt[BATCH];
       const int bn = (b0 + BATCH < kTile) ? b0 + BATCH : b0;  // (last batch: a harmless reload)
-      static_for<0, BATCH>([&](auto JB) Q2X_INLINE {
-        constexpr int j = decltype(JB)::value;
-        nxt[j] = pv[bn + j];
-      });
+      load_batch(bn, nxt);
       const uint32_t uc = (uint32_t)(cuts >> b0) & 0xffu;
       static_for<0, BATCH>([&](auto JB) Q2X_INLINE {
         constexpr int j = decltype(JB)::value;
