@@ -17,6 +17,15 @@
 //                on the 8 digit bits) plus a per-digit running count across the
 //                waves of the chunk, taken in element order -- so the sort is
 //                stable and deterministic.
+// With few boxes (B + 1 <= 1024 bins) and up to 2^17 elements one pass of a
+// counting sort on the whole (clamped) key replaces the 8-bit passes, with the
+// same three steps: per chunk of 2048 elements a histogram over all B + 1 bins
+// (in LDS), the same row scan, and a scatter that ranks equal keys with
+// wavefront ballots (match on all key bits) and a per-bin running position
+// advanced wave by wave in element order.  Same stable order, three kernels
+// instead of up to six.  (With more bins the scatter's bin scan and its
+// wave-serial steps cost more than the second radix pass saves: measured
+// slower at 6,617 boxes and 81,920 elements.)
 // The box start table is written by the tile kernel (it reads every sorted key
 // and its predecessor anyway); box_bounds is used by the standalone entry point.
 #include "q2x_internal.hpp"
@@ -177,6 +186,110 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter(const int32_t* __r
   }
 }
 
+// ---- one-pass counting sort (few boxes)
+constexpr int kCsThreads = 1024;
+constexpr int kCsSub = 2;                      // sub-rounds of kCsThreads elements per chunk
+constexpr int kCsChunk = kCsThreads * kCsSub;  // 2048 elements per workgroup
+constexpr int kCsMaxBins = 1024;               // box ids 0..B-1 and the invalid bin B
+constexpr int64_t kCsMaxN = (int64_t)1 << 17;
+
+bool counting_sort_applies(int64_t n, int64_t nb) { return nb + 1 <= kCsMaxBins && n <= kCsMaxN; }
+
+// Chunk histogram over all bins; workgroup 0 also clears the status block.
+__global__ __launch_bounds__(kCsThreads) void cs_hist(const int32_t* __restrict__ keys, int64_t n, int64_t nb,
+                                                     int32_t* __restrict__ counts, int64_t n_chunks,
+                                                     Status* status) {
+  __shared__ int32_t h[kCsMaxBins];
+  const int t = threadIdx.x;
+  const int nbins = (int)nb + 1;
+  if (blockIdx.x == 0 && t < (int)(sizeof(Status) / 4)) reinterpret_cast<uint32_t*>(status)[t] = 0u;
+  for (int i = t; i < nbins; i += kCsThreads) h[i] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kCsChunk;
+#pragma unroll
+  for (int j = 0; j < kCsSub; ++j) {
+    const int64_t i = base + j * kCsThreads + t;
+    if (i < n) atomicAdd(&h[clamp_key(keys[i], nb)], 1);
+  }
+  __syncthreads();
+  for (int i = t; i < nbins; i += kCsThreads) counts[(int64_t)i * n_chunks + blockIdx.x] = h[i];
+}
+
+// Stable scatter: element i of the chunk goes to (start of its bin) + (number
+// of earlier elements of the chunk in the bin), the latter from the wavefront
+// match of all nbits key bits and the bin's running position, which the
+// waves advance one after the other.  Ids outside [0, B) are counted.
+__global__ __launch_bounds__(kCsThreads) void cs_scatter(const int32_t* __restrict__ keys, int64_t n, int64_t nb,
+                                                        int nbits, const int32_t* __restrict__ rows,
+                                                        const int32_t* __restrict__ totals, int64_t n_chunks,
+                                                        int32_t* __restrict__ keys_out,
+                                                        int32_t* __restrict__ vals_out, Status* status) {
+  __shared__ int32_t pos_of[kCsMaxBins];  // next output position of each bin for this chunk
+  __shared__ int32_t sh[kCsThreads];
+  __shared__ int32_t carry;
+  const int t = threadIdx.x;
+  const int lane = t & 63, w = t >> 6;
+  const int nbins = (int)nb + 1;
+  // pos_of[b] = (exclusive scan of the bin totals)[b] + (this chunk's row offset of b)
+  if (t == 0) carry = 0;
+  for (int b0 = 0; b0 < nbins; b0 += kCsThreads) {
+    const int b = b0 + t;
+    const int32_t v = (b < nbins) ? totals[b] : 0;
+    __syncthreads();
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kCsThreads; off <<= 1) {
+      const int32_t x = (t >= off) ? sh[t - off] : 0;
+      __syncthreads();
+      sh[t] += x;
+      __syncthreads();
+    }
+    if (b < nbins) pos_of[b] = carry + sh[t] - v + rows[(int64_t)b * n_chunks + blockIdx.x];
+    __syncthreads();
+    if (t == kCsThreads - 1) carry += sh[t];
+  }
+  __syncthreads();
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int64_t cbase = (int64_t)blockIdx.x * kCsChunk;
+  int bad = 0;
+  for (int j = 0; j < kCsSub; ++j) {
+    const int64_t i = cbase + j * kCsThreads + t;
+    const bool valid = i < n;
+    int32_t key = 0;
+    if (valid) {
+      const int32_t k0 = keys[i];
+      bad += (k0 < 0 || k0 >= nb);
+      key = clamp_key(k0, nb);
+    }
+    uint64_t peers = __ballot(valid);
+    for (int b = 0; b < nbits; ++b) {
+      const bool bit = (key >> b) & 1;
+      const uint64_t m = __ballot(valid && bit);
+      peers &= bit ? m : ~m;
+    }
+    const int rank = __popcll(peers & lt_mask);
+    const int cnt = __popcll(peers);
+    for (int ww = 0; ww < kCsThreads / 64; ++ww) {
+      if (w == ww && valid) {
+        const int32_t start = pos_of[key];  // every lane reads before the leaders advance
+        keys_out[start + rank] = key;
+        vals_out[start + rank] = (int32_t)i;
+        if (rank == 0) pos_of[key] = start + cnt;
+      }
+      __syncthreads();
+    }
+  }
+  const uint64_t m = __ballot(bad != 0);
+  if (m) {
+    int c = bad;
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off);
+    if (lane == 0) {
+      atomicAdd(&status->n_skipped, (unsigned long long)c);
+      atomicOr(&status->flags, (uint32_t)Q2X_FLAG_BAD_BOX);
+    }
+  }
+}
+
 // box_start[b] = first sorted position whose key >= b, for b in [0, B];
 // keys outside [0, B) count as -1 (before everything) or B (after).  With
 // `order_check`, a decrease of the (clamped) keys sets Q2X_FLAG_NOT_SORTED.
@@ -214,8 +327,13 @@ int radix_passes(int64_t n_boxes) {
 
 size_t bucket_scratch_bytes(int64_t n, int64_t nb) {
   const int64_t n_chunks = (n + kChunk - 1) / kChunk;
-  (void)nb;
-  return (size_t)(4 * n + (int64_t)kBins * (n_chunks > 0 ? n_chunks : 1) + kBins) * sizeof(int32_t);
+  int64_t words = 4 * n + (int64_t)kBins * (n_chunks > 0 ? n_chunks : 1) + kBins;
+  if (counting_sort_applies(n, nb)) {
+    const int64_t cs_chunks = (n + kCsChunk - 1) / kCsChunk;
+    const int64_t cs = 2 * n + (nb + 1) * (cs_chunks > 0 ? cs_chunks : 1) + (nb + 1);
+    if (cs > words) words = cs;
+  }
+  return (size_t)words * sizeof(int32_t);
 }
 
 // Sort elem_box -> (keys, perm); the first kernel also clears the status
@@ -223,6 +341,23 @@ size_t bucket_scratch_bytes(int64_t n, int64_t nb) {
 // permutation.
 hipError_t bucket_elements(const int32_t* elem_box, int64_t n, int64_t nb, int32_t* scratch, Status* status,
                            hipStream_t s, const int32_t** keys_out, const int32_t** perm_out) {
+  if (counting_sort_applies(n, nb)) {
+    const int64_t cs_chunks = (n + kCsChunk - 1) / kCsChunk;
+    int32_t* ko = scratch;
+    int32_t* vo = ko + n;
+    int32_t* counts = vo + n;
+    int32_t* tot = counts + (nb + 1) * cs_chunks;
+    int nbits = 1;
+    while (nbits < 31 && ((int64_t)1 << nbits) <= nb) ++nbits;  // keys in [0, nb]
+    hipLaunchKernelGGL(cs_hist, dim3((unsigned)cs_chunks), dim3(kCsThreads), 0, s, elem_box, n, nb, counts,
+                       cs_chunks, status);
+    hipLaunchKernelGGL(radix_rowscan, dim3((unsigned)(nb + 1)), dim3(kSortThreads), 0, s, counts, cs_chunks, tot);
+    hipLaunchKernelGGL(cs_scatter, dim3((unsigned)cs_chunks), dim3(kCsThreads), 0, s, elem_box, n, nb, nbits, counts,
+                       tot, cs_chunks, ko, vo, status);
+    *keys_out = ko;
+    *perm_out = vo;
+    return hipGetLastError();
+  }
   const int64_t n_chunks = (n + kChunk - 1) / kChunk;
   int32_t* ka = scratch;
   int32_t* va = ka + n;
