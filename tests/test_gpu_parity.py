@@ -93,7 +93,9 @@ def test_bucket_bit_exact():
     import oracle
     from paper_2107_10942_amd import q2x
     rng = np.random.default_rng(7)
-    for n, nb in [(0, 5), (1, 1), (63, 3), (1000, 37), (5000, 300), (70000, 70000), (200000, 4400)]:
+    # one-pass counting sort up to B + 1 = 1024 bins and n = 2^17 (chunks of 2048), radix passes beyond
+    for n, nb in [(0, 5), (1, 1), (63, 3), (1000, 37), (2049, 700), (5000, 300), (131072, 1023), (131073, 1023),
+                  (50000, 1024), (70000, 70000), (200000, 4400)]:
         eb = rng.integers(-3, nb + 3, size=n).astype(np.int32) if n else np.zeros(0, np.int32)
         perm, bs, ws = q2x.bucket(torch.as_tensor(eb).cuda(), nb)
         f, _, skipped = q2x.status(ws)
