@@ -13,6 +13,9 @@
 //   x_q = (r - x_q).i_q,  z_q = (r - x_q).n_q,
 //   M_P(x, y, z) = -atan(x z (R - y) / (R z^2 + y x^2)),
 //   L_P(x, y, z) = -y M_P(x, y, z) - z ln(R + x),  R = sqrt(x^2 + y^2 + z^2).
+// Per edge the two ends combine: the M_P difference is the argument of a
+// product of two complex numbers (one atan2) and the ln difference the log
+// of a ratio.
 // The printed M lacks the factor sign(hs): with h = |hs| the contour sum is
 // the value on the +n side, and M is odd in hs.  R - y and R + x (x < 0) are
 // formed without cancellation as (x^2 + z^2)/(R + y) and (y^2 + z^2)/(R - x);
@@ -47,19 +50,18 @@ struct NearArgs {
 
 constexpr double kInv4PiNear = 0.07957747154594766788;
 
-__device__ __forceinline__ double near_MP(double x, double y, double z) {
-  if (z == 0.0) return 0.0;
+// One end of an edge (z != 0): M_P = -atan(N / D) with N = x z (R - y) and
+// D = R z^2 + y x^2 >= 0, and R + x, all without cancellation.
+struct NearEnd {
+  double N, D, Rpx;
+};
+__device__ __forceinline__ NearEnd near_end(double x, double y, double z) {
   const double R = sqrt(x * x + y * y + z * z);
-  const double Rmy = (x * x + z * z) / (R + y);  // R - y, y >= 0
-  const double den = R * z * z + y * x * x;      // > 0 for z != 0
-  return -atan(x * z * Rmy / den);
-}
-
-__device__ __forceinline__ double near_LP(double x, double y, double z, double mp) {
-  if (z == 0.0) return -y * mp;
-  const double R = sqrt(x * x + y * y + z * z);
-  const double Rpx = (x >= 0.0) ? R + x : (y * y + z * z) / (R - x);  // > 0 for z != 0
-  return -y * mp - z * log(Rpx);
+  NearEnd e;
+  e.N = x * z * ((x * x + z * z) / (R + y));                 // R - y = (x^2 + z^2)/(R + y), y >= 0
+  e.D = R * z * z + y * x * x;
+  e.Rpx = (x >= 0.0) ? R + x : (y * y + z * z) / (R - x);  // > 0 for z != 0
+  return e;
 }
 
 // Cross product without contraction into FMAs: parallel edge vectors (a
@@ -83,7 +85,8 @@ __device__ bool near_pair(const double* r, const double (&X)[3][3], double& L, d
   L = 0.0;
   M = 0.0;
   if (!(J > 0.0)) return false;
-  const double nx = cx / J, ny = cy / J, nz = cz / J;
+  const double iJ = 1.0 / J;
+  const double nx = cx * iJ, ny = cy * iJ, nz = cz * iJ;
   double l2max = 0.0;
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
@@ -100,15 +103,23 @@ __device__ bool near_pair(const double* r, const double (&X)[3][3], double& L, d
     const int q1 = (q + 1) % 3;
     const double ex = X[q1][0] - X[q][0], ey = X[q1][1] - X[q][1], ez = X[q1][2] - X[q][2];
     const double l = sqrt(ex * ex + ey * ey + ez * ez);
-    const double ix = ex / l, iy = ey / l, iz = ez / l;
+    const double il = 1.0 / l;
+    const double ix = ex * il, iy = ey * il, iz = ez * il;
     // n_q = i_q x n
     const double mx = iy * nz - iz * ny, my = iz * nx - ix * nz, mz = ix * ny - iy * nx;
     const double dx = r[0] - X[q][0], dy = r[1] - X[q][1], dz = r[2] - X[q][2];
     const double xq = dx * ix + dy * iy + dz * iz;
     const double zq = dx * mx + dy * my + dz * mz;
-    const double m1 = near_MP(l - xq, h, zq), m0 = near_MP(-xq, h, zq);
-    sM += m1 - m0;
-    sL += near_LP(l - xq, h, zq, m1) - near_LP(-xq, h, zq, m0);
+    if (zq == 0.0) continue;  // both ends' terms vanish
+    // M_P(l - x) - M_P(-x) = atan(N0/D0) - atan(N1/D1) = arg((D0 + i N0) conj(D1 + i N1)),
+    // exact for D0, D1 >= 0 (both angles in [-pi/2, pi/2]); one atan2 and one
+    // log of a ratio per edge instead of two of each
+    const NearEnd e1 = near_end(l - xq, h, zq), e0 = near_end(-xq, h, zq);
+    // (N and D scale as the cube of the coordinates: their products stay in
+    // range for coordinates below ~1e50)
+    const double dm = atan2(e0.N * e1.D - e0.D * e1.N, e0.D * e1.D + e0.N * e1.N);
+    sM += dm;
+    sL += -h * dm - zq * log(e1.Rpx / e0.Rpx);
   }
   L = sL * kInv4PiNear;
   M = (hs > 0.0 ? sM : (hs < 0.0 ? -sM : 0.0)) * kInv4PiNear;
