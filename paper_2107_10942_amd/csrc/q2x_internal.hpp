@@ -23,6 +23,18 @@ struct Status {
 };
 static_assert(sizeof(Status) == 64, "status block is 64 bytes");
 
+// Global-memory view of a device pointer.  A pointer picked at run time from
+// an argument struct or a job table is generic to the compiler, which then
+// emits FLAT accesses; a FLAT store also counts against the LDS wait counter,
+// so the next wait for LDS reads would wait for the store to reach memory.
+// Accesses through this view are GLOBAL (vector-memory counter only).
+typedef __attribute__((address_space(1))) double gdouble;
+typedef const __attribute__((address_space(1))) double cgdouble;
+typedef const __attribute__((address_space(1))) int32_t cgint;
+__device__ __forceinline__ gdouble* as_global(double* p) { return (gdouble*)p; }
+__device__ __forceinline__ cgdouble* as_global(const double* p) { return (cgdouble*)p; }
+__device__ __forceinline__ cgint* as_global(const int32_t* p) { return (cgint*)p; }
+
 // Number of m >= 0 ("tilde") coefficients of degrees 0..n-1.
 __host__ __device__ constexpr int tri(int n) { return n * (n + 1) / 2; }
 
@@ -141,8 +153,9 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t nblk) {
 //   MOMENT: M_n^{m}  = (-1)^m 4pi i^{m} T,     M_n^{-m} = (-1)^m 4pi i^{m} conj(T)
 // (tilde <-> plain: Sec. 3.4, Eqs. (47),(49); symmetry Eq. (12); weights Eq. (20)).
 // Branch-free in m (lanes of a wavefront hold different orders).
-__device__ __forceinline__ void finalize_store(double* row, int n, int m, double tr, double ti, int norm,
+__device__ __forceinline__ void finalize_store(double* row_generic, int n, int m, double tr, double ti, int norm,
                                                int accumulate) {
+  gdouble* const row = as_global(row_generic);
   const int r = m & 3;
   const double c = (r == 0) ? 1.0 : ((r == 2) ? -1.0 : 0.0);
   const double s = (r == 1) ? -1.0 : ((r == 3) ? 1.0 : 0.0);

@@ -266,19 +266,21 @@ __device__ __forceinline__ ElemGeom<NV, T> element_geometry(const double* verts,
   if (ok) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-      const int32_t vi = elems[e * NV + k];
+      const int32_t vi = as_global(elems)[e * NV + k];
       if (vi < 0 || vi >= n_verts) {
         ok = false;
         g.flag |= Q2X_FLAG_BAD_VERTEX;
       } else {
-        xv[k][0] = verts[3 * (int64_t)vi];
-        xv[k][1] = verts[3 * (int64_t)vi + 1];
-        xv[k][2] = verts[3 * (int64_t)vi + 2];
+        cgdouble* const vp = as_global(verts) + 3 * (int64_t)vi;
+        xv[k][0] = vp[0];
+        xv[k][1] = vp[1];
+        xv[k][2] = vp[2];
       }
     }
-    cx = box_center[3 * (int64_t)key];
-    cy = box_center[3 * (int64_t)key + 1];
-    cz = box_center[3 * (int64_t)key + 2];
+    cgdouble* const cp = as_global(box_center) + 3 * (int64_t)key;
+    cx = cp[0];
+    cy = cp[1];
+    cz = cp[2];
   }
   if (ok) {
     bool fin = isfinite(cx) && isfinite(cy) && isfinite(cz);
@@ -423,7 +425,7 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
   const int64_t e = in_range ? (a.perm ? (int64_t)a.perm[q] - elem_off : q) : 0;
   double sigma[NOUT];
 #pragma unroll
-  for (int o = 0; o < NOUT; ++o) sigma[o] = box_ok ? a.dens[o][e * a.dstride] : 0.0;
+  for (int o = 0; o < NOUT; ++o) sigma[o] = box_ok ? as_global(a.dens[o])[e * a.dstride] : 0.0;
   const ElemGeom<NV, T> gm = element_geometry<NV, T, SCALED>(a.verts, a.n_verts, a.elems, e, a.box_center, key,
                                                              box_ok, sigma, NOUT);
   const bool ok = gm.ok;
@@ -603,7 +605,7 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
       const double ti = __hiloint2double((int)shi[1], (int)slo[1]);
       if ((seg == 0 && head_open) || (sb == kTile && tail_open)) {  // uniform: box continues in another tile
         if (h == 0 && live) {
-          double* pp = pbase + ((seg == 0) ? 0 : (int64_t)(NOUT * NCT) * 2);
+          gdouble* pp = as_global(pbase + ((seg == 0) ? 0 : (int64_t)(NOUT * NCT) * 2));
           pp[0] = tr;
           pp[1] = ti;
         }
@@ -611,7 +613,7 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
       }
       if (!wr) return;
       double x = A1 * tr + A2 * ti, y = B1 * tr + B2 * ti;
-      double* dst = obase + (int64_t)box * ncoef_out * 2;
+      gdouble* dst = as_global(obase + (int64_t)box * ncoef_out * 2);
       if (a.accumulate) {
         x += dst[0];
         y += dst[1];
