@@ -26,7 +26,6 @@ __global__ __launch_bounds__(256) void q2x_fixup_kernel(FixupArgs f) {
   const int lane = threadIdx.x & 63;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  const int64_t ncoef = (int64_t)(f.p + 1) * (f.p + 1);
   for (int64_t b = wave; b < f.n_boxes; b += nwaves) {
     const int64_t s = f.n_pos ? f.box_start[b] : 0, t = f.n_pos ? f.box_start[b + 1] : 0;
     fixup_box(lane, s, t, 0, 0, f.partials, f.outs, b, f.nout, f.p, f.P, f.norm, f.accumulate);
@@ -77,19 +76,19 @@ Prof& prof() {
   return p;
 }
 
-Prof::Ev get_ev() {
+// A set of four timing events (from the pool, else new); false if HIP could
+// not create them (the call then runs untimed).
+bool get_ev(Prof::Ev& e) {
   Prof& P = prof();
   if (!P.pool.empty()) {
-    Prof::Ev e = P.pool.back();
+    e = P.pool.back();
     P.pool.pop_back();
-    return e;
+    return true;
   }
-  Prof::Ev e;
-  hipEventCreate(&e.a);
-  hipEventCreate(&e.b);
-  hipEventCreate(&e.c);
-  hipEventCreate(&e.d);
-  return e;
+  if (hipEventCreate(&e.a) != hipSuccess || hipEventCreate(&e.b) != hipSuccess ||
+      hipEventCreate(&e.c) != hipSuccess || hipEventCreate(&e.d) != hipSuccess)
+    return false;
+  return true;
 }
 
 // One call.  Output o (o < outputs of the kind) takes its density from
@@ -139,10 +138,9 @@ q2x_status run(int kind, const double* verts, int64_t n_verts, const int32_t* el
   bool timing = false;
   {
     std::lock_guard<std::mutex> g(PR.mu);
-    timing = PR.on;
-    if (timing) ev = get_ev();
+    timing = PR.on && get_ev(ev);
   }
-  if (timing) hipEventRecord(ev.a, s);
+  if (timing && hipEventRecord(ev.a, s) != hipSuccess) return Q2X_ERR_HIP;
 
   // status clear + bucketing (the first sort kernel clears the status block);
   // the tile kernel writes the box start table
@@ -175,12 +173,12 @@ q2x_status run(int kind, const double* verts, int64_t n_verts, const int32_t* el
   a.norm = norm;
   a.accumulate = (flags & Q2X_ACCUMULATE) ? 1 : 0;
   const int64_t n_tiles = (n_elems + kTile - 1) / kTile;
-  if (timing) hipEventRecord(ev.b, s);
+  if (timing && hipEventRecord(ev.b, s) != hipSuccess) return Q2X_ERR_HIP;
   if (n_tiles > 0) {
     err = launch_tiles(kind, prec, P, a, n_tiles, s);
     if (err != hipSuccess) return Q2X_ERR_HIP;
   }
-  if (timing) hipEventRecord(ev.c, s);
+  if (timing && hipEventRecord(ev.c, s) != hipSuccess) return Q2X_ERR_HIP;
   if (n_boxes > 0) {
     FixupArgs f{};
     f.box_start = box_start;
@@ -200,7 +198,7 @@ q2x_status run(int kind, const double* verts, int64_t n_verts, const int32_t* el
     if (hipGetLastError() != hipSuccess) return Q2X_ERR_HIP;
   }
   if (timing) {
-    hipEventRecord(ev.d, s);
+    if (hipEventRecord(ev.d, s) != hipSuccess) return Q2X_ERR_HIP;
     ev.kind = kind;
     std::lock_guard<std::mutex> g(PR.mu);
     PR.evs.push_back(ev);
