@@ -503,6 +503,9 @@ def main():
                            "fp64_ms_per_step": separate[q2x.FP64]["ms_per_step"],
                            "per_kind_mixed": separate[q2x.FP32_MIXED]["per_kind"]},
         "speedup_mixed_vs_fp64": plain["ms_per_step"] / mixed["ms_per_step"],
+        # box coefficients written per second (occupied boxes x (p+1)^2, both layers)
+        "box_coefficients_per_s": {"fp32_mixed": 2 * B * (p + 1) ** 2 / (mixed["ms_per_step"] * 1e-3),
+                                   "fp64": 2 * B * (p + 1) ** 2 / (plain["ms_per_step"] * 1e-3)},
         "per_kind_mixed": mixed["per_kind"],
         "mixed_vs_fp64_max_rel_diff": agree,
         "status_flags": {"mixed": mixed["flags"], "fp64": plain["flags"]},
@@ -586,6 +589,19 @@ def main():
                 table[f"{name}_{layer}"] = error_stats(res[layer][bx], refs[job.kind], en, job.density[keep],
                                                        job.elem_box[keep], bx, p)
         line["cpu_baseline"]["error_vs_oracle"] = table
+        # the same oracle on one thread, on every 40th box (context for the all-core figure;
+        # last, as the thread count it sets stays in force)
+        bx1 = np.arange(0, B, 40)
+        keep1 = np.isin(single.elem_box, bx1)
+        t0 = time.perf_counter()
+        for job in (single, double):
+            oracle.q2x(job.kind, p, job.verts, job.elems[keep1], job.density[keep1], job.elem_box[keep1],
+                       job.box_center, boxes=bx1, threads=1)
+        dt1 = time.perf_counter() - t0
+        line["cpu_baseline"]["one_thread"] = {"value": 2 * int(keep1.sum()) * (p + 1) ** 2 / dt1,
+                                              "unit": "coefficients/s", "cores": 1,
+                                              "sample": f"every 40th box ({len(bx1)} boxes, {int(keep1.sum())} "
+                                                        f"triangles), {dt1:.1f} s"}
     print(json.dumps(line), flush=True)
 
 
