@@ -173,6 +173,11 @@ q2x_status run(int kind, const double* verts, int64_t n_verts, const int32_t* el
   a.norm = norm;
   a.accumulate = (flags & Q2X_ACCUMULATE) ? 1 : 0;
   const int64_t n_tiles = (n_elems + kTile - 1) / kTile;
+  // small grids leave the chip latency-bound: there two workgroups share a
+  // tile's chunks (each runs the recursion).  Measured: FP64 gains up to two
+  // tiles per SIMD (1,024 SIMDs); FP32, whose recursion is the cheaper half
+  // of a wave, only up to half a tile per SIMD
+  a.nsplit = (n_tiles <= (prec == Q2X_FP64 ? 2048 : 512)) ? 2 : 1;
   if (timing && hipEventRecord(ev.b, s) != hipSuccess) return Q2X_ERR_HIP;
   if (n_tiles > 0) {
     err = launch_tiles(kind, prec, P, a, n_tiles, s);

@@ -62,6 +62,8 @@ struct TileArgs {
   int p;                     // requested order (<= template P)
   int norm;
   int accumulate;
+  int nsplit;                // workgroups per tile (0 or 1: one); workgroup w of a tile stages and
+                             // reduces the chunks J with J % nsplit == w (the grid holds n_tiles * nsplit)
   // batch launch (nullptr otherwise)
   const BatchJob* bjobs;       // job table
   const int32_t* bgroup_jobs;  // [bng] jobs of this launch

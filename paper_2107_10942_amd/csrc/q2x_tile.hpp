@@ -374,7 +374,14 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
   // element scales a_e, row 1 + o: the weights s_e of output o)
   __shared__ int sexp[SCALED ? (NOUT + 1) * kTile : 1];
 
-  const int64_t tile = xcd_tile(blockIdx.x, n_tiles);
+  // with nsplit > 1 a tile has nsplit workgroups (consecutive virtual ids, so
+  // the same XCD): all run the recursion, workgroup wpart stages and reduces
+  // the chunks J with J % nsplit == wpart -- shorter waves for grids too small
+  // to fill the chip, bitwise the same sums
+  const int ns = (args.nsplit > 1) ? args.nsplit : 1;
+  const int64_t vb = xcd_tile(blockIdx.x, n_tiles * ns);
+  const int64_t tile = vb / ns;
+  const int wpart = (int)(vb % ns);
   const int lane = threadIdx.x;
   TileArgs a = args;
   int64_t q0 = tile * kTile;   // first sorted position of the tile
@@ -447,7 +454,7 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
   // ---- box start table: box_start[b] = first position whose key >= b, keys
   // outside [0, B) counting as -1 / B (the fix-up kernel reads it)
   const int key_prev = (in_range && q > 0) ? (int)(a.keys[q - 1] - key_off) : INT32_MIN;
-  if (in_range && !batch) {
+  if (in_range && !batch && wpart == 0) {
     const int64_t nb = a.n_boxes;
     const int64_t kc = key < 0 ? -1 : (key >= nb ? nb : key);
     const int64_t kp = (q == 0 || key_prev < 0) ? -1 : (key_prev >= nb ? nb : key_prev);
@@ -465,7 +472,7 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
 #pragma unroll
     for (int b = 0; b < 5; ++b)
       if (__ballot((flag >> b) & 1u)) fall |= (1u << b);
-    if (lane == 0) {
+    if (lane == 0 && wpart == 0) {
       if (deg_mask) atomicAdd(&a.status->n_degenerate, (unsigned long long)__popcll(deg_mask));
       if (skip_mask) atomicAdd(&a.status->n_skipped, (unsigned long long)__popcll(skip_mask));
       if (fall) atomicOr(&a.status->flags, fall);
@@ -731,6 +738,7 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
       constexpr int m = decltype(MM)::value;
       constexpr int kk = k0 + m;
       constexpr int row = kk % CMAX;
+      if ((kk / CMAX) % ns != wpart) return;  // uniform: another workgroup's chunk
       stage[row * SSTR + lane] = V.r[m] * w;
       stage[(CMAX + row) * SSTR + lane] = V.i[m] * w;
       if constexpr (row == CMAX - 1) reduce_chunk(IC<kk / CMAX>{});  // chunk kk / CMAX is full
@@ -741,7 +749,9 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
       constexpr double inv_next = 1.0 / (double)(N + 1 + KI::depth(o));
       wgt[o] *= inv_next;
     }
-    if constexpr (k1 % CMAX != 0 && k1 == Plan::K) reduce_chunk(IC<j1>{});  // last, partly filled chunk
+    if constexpr (k1 % CMAX != 0 && k1 == Plan::K) {  // last, partly filled chunk
+      if (j1 % ns == wpart) reduce_chunk(IC<j1>{});
+    }
   };
 
   // one degree of every array of the chain: nS (degree N) from S (degree N-1)
@@ -824,7 +834,7 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
   // of degree p unless it ended exactly there
   if (p < P) {
     const int kend = NOUT * tri(p + 1);
-    if (kend % CMAX != 0) {
+    if (kend % CMAX != 0 && ((kend - 1) / CMAX) % ns == wpart) {
       const int J = (kend - 1) / CMAX;
       const int K0 = J * CMAX;
       const int CJ = min(CMAX, Plan::K - K0);
