@@ -162,9 +162,17 @@ def other_workloads(dev, reps=20):
             k = job.kind
             kern = rec_ms[k] / calls[k]
             fl = flops.launch_flops(k, job.p, job.n_elems)
+            # binding roof: min(VALU peak, arithmetic intensity x HBM peak)
+            by = flops.launch_bytes(k, job.p, job.n_elems, job.n_boxes)
+            ai = fl / by
+            hbm_bound = ai < flops.PEAK_VALU_TFLOPS * 1e12 / (flops.PEAK_HBM_GBS * 1e9)
+            ach_tf = fl / (kern * 1e-3) / 1e12
+            ach_gbs = by / (kern * 1e-3) / 1e9
             res[pn] = {"call_ms": dt * 1e3, "kernel_ms": kern,
                        "coefficients_per_s": job.n_elems * (job.p + 1) ** 2 / dt,
-                       "kernel_tflops": fl / (kern * 1e-3) / 1e12}
+                       "kernel_tflops": ach_tf, "kernel_gbs": ach_gbs, "flop_per_byte": ai,
+                       "bound": "hbm" if hbm_bound else "alu",
+                       "frac": (ach_gbs / flops.PEAK_HBM_GBS) if hbm_bound else (ach_tf / flops.PEAK_VALU_TFLOPS)}
         out[name] = res
     # the random walks again with a vector density (walk tangent x strength): three outputs, one recursion
     import numpy as np
