@@ -203,7 +203,8 @@ q2x_status q2x_bucket(const int32_t* elem_box, int64_t n_elems, int64_t n_boxes,
 /*
  * Receiving side: integrals of local expansions over elements, the evaluation
  * stage of a Galerkin method, which uses the same element integrals as Q2X
- * (Sec. 2 after Eq. (5); the recursions of Sec. 3.4, Eqs. (50)-(56)).
+ * (Sec. 2 after Eq. (5) and the Conclusions; the recursions of Sec. 3.4,
+ * Eqs. (50)-(56)).
  *   kind       Q2X_TRI_SINGLE (int_e R_n^m dS), Q2X_TRI_DOUBLE
  *              (int_e n . grad_y R_n^m dS, n the unit normal (x2-x1) x (x3-x1)),
  *              Q2X_SEGMENT (int_e R_n^m ds) or Q2X_TET (int_e R_n^m dV)

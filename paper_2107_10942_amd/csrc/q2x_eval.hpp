@@ -1,6 +1,8 @@
 // q2x_eval.hpp -- the receiving side: integrals of a local expansion over
-// elements (the evaluation stage of a Galerkin method, which the paper notes
-// uses the same integrals; Sec. 2 after Eq. (5)).
+// elements (the evaluation stage of a Galerkin method, which uses the same
+// integrals: Sec. 2 after Eq. (5), and the Conclusions, where the far field
+// of a Galerkin FMM is a series in R_n^m to be integrated over the receiving
+// triangles).
 //
 // For element e of box b with local coefficients L_b (a field
 // sum_{n<=p, |m|<=n} L_{b,n}^m R_n^m(y - c_b)):
