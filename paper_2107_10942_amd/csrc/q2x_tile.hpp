@@ -545,9 +545,10 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
   // two partial sums, added where a box segment ends).  Box changes are
   // therefore the same for every lane; at each one the wave pairs the real and
   // imaginary sums across the halves (v_permlane32_swap) and lane c stores
-  // coefficient +m, lane c + 32 the coefficient -m.  The walk loads 8 elements
-  // ahead; the box id and scale exponents of a new segment come from the lane
-  // of its first element (readlane), so a segment end touches no LDS.
+  // coefficient +m, lane c + 32 the coefficient -m.  The walk reads each half
+  // of the next 8 elements as soon as the same half of the current 8 is
+  // summed; the box id and scale exponents of a new segment come from the
+  // lane of its first element (readlane), so a segment end touches no LDS.
   // Elements past ne carry weight 0 and add exact zeros.
   const uint64_t cuts = bnd & ~1ull;  // bit i: a box segment ends before element i
   // Reduction of the chunk with first slot K0 (CJ slots); the lane's slot
@@ -638,36 +639,40 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
       }
     };
     const T* pv = stage + ((h ? CMAX : 0) + (act ? c : 0)) * SSTR;
-    // BATCH consecutive staged values of the lane's row in 16-byte reads
-    auto load_batch = [&](int off, T (&dst)[BATCH]) Q2X_INLINE {
+    // Half H (BATCH / 2 consecutive staged values from position off + H BATCH / 2)
+    // of the lane's row, in 16-byte reads, into dst[H BATCH / 2 ...]
+    auto load_half = [&](auto HH, int off, T (&dst)[BATCH]) Q2X_INLINE {
+      constexpr int H = decltype(HH)::value;
+      constexpr int B2 = BATCH / 2;
       if constexpr (sizeof(T) == 4) {
-        const float4* q = reinterpret_cast<const float4*>(pv + off);
-        static_for<0, BATCH / 4>([&](auto II) Q2X_INLINE {
+        const float4* q = reinterpret_cast<const float4*>(pv + off + H * B2);
+        static_for<0, B2 / 4>([&](auto II) Q2X_INLINE {
           constexpr int i = decltype(II)::value;
           const float4 v = q[i];
-          dst[4 * i] = v.x;
-          dst[4 * i + 1] = v.y;
-          dst[4 * i + 2] = v.z;
-          dst[4 * i + 3] = v.w;
+          dst[H * B2 + 4 * i] = v.x;
+          dst[H * B2 + 4 * i + 1] = v.y;
+          dst[H * B2 + 4 * i + 2] = v.z;
+          dst[H * B2 + 4 * i + 3] = v.w;
         });
       } else {
-        const double2* q = reinterpret_cast<const double2*>(pv + off);
-        static_for<0, BATCH / 2>([&](auto II) Q2X_INLINE {
+        const double2* q = reinterpret_cast<const double2*>(pv + off + H * B2);
+        static_for<0, B2 / 2>([&](auto II) Q2X_INLINE {
           constexpr int i = decltype(II)::value;
           const double2 v = q[i];
-          dst[2 * i] = v.x;
-          dst[2 * i + 1] = v.y;
+          dst[H * B2 + 2 * i] = v.x;
+          dst[H * B2 + 2 * i + 1] = v.y;
         });
       }
     };
     double a0 = 0.0, a1 = 0.0;  // sums over even / odd positions of the open segment
+    // cur holds the batch being summed; each half is refilled from the next
+    // batch as soon as it has been summed (no second buffer, no copies)
     T cur[BATCH];
-    load_batch(0, cur);
+    load_half(IC<0>{}, 0, cur);
+    load_half(IC<1>{}, 0, cur);
 #pragma unroll 1
     for (int b0 = 0; b0 < kTile; b0 += BATCH) {  // uniform
-      T nxt[BATCH];
       const int bn = (b0 + BATCH < kTile) ? b0 + BATCH : b0;  // (last batch: a harmless reload)
-      load_batch(bn, nxt);
       const uint32_t uc = (uint32_t)(cuts >> b0) & 0xffu;
       static_for<0, BATCH>([&](auto JB) Q2X_INLINE {
         constexpr int j = decltype(JB)::value;
@@ -681,10 +686,8 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
           a1 += (double)cur[j];
         else
           a0 += (double)cur[j];
-      });
-      static_for<0, BATCH>([&](auto JB) Q2X_INLINE {
-        constexpr int j = decltype(JB)::value;
-        cur[j] = nxt[j];
+        if constexpr (j == BATCH / 2 - 1) load_half(IC<0>{}, bn, cur);
+        if constexpr (j == BATCH - 1) load_half(IC<1>{}, bn, cur);
       });
     }
     flush(ne, a0 + a1);  // the tile's last segment
