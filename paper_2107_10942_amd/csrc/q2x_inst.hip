@@ -24,7 +24,7 @@ using RealT = double;
 #endif
 
 hipError_t Q2X_LAUNCHER(int P, const TileArgs& a, int64_t n_tiles, hipStream_t s) {
-  const dim3 grid((unsigned)(n_tiles * (a.nsplit > 1 ? a.nsplit : 1))), block(kTile);
+  const dim3 grid((unsigned)(n_tiles + a.n_split)), block(kTile);
   switch (P) {
 #define Q2X_CASE(PP)                                                                         \
   case PP:                                                                                   \

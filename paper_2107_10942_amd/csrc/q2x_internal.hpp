@@ -62,8 +62,10 @@ struct TileArgs {
   int p;                     // requested order (<= template P)
   int norm;
   int accumulate;
-  int nsplit;                // workgroups per tile (0 or 1: one); workgroup w of a tile stages and
-                             // reduces the chunks J with J % nsplit == w (the grid holds n_tiles * nsplit)
+  int64_t n_split;           // tiles that get two workgroups (0 <= n_split <= n_tiles <= 2048 when > 0; spread evenly:
+                             // tile t is split iff floor((t+1) n_split / n_tiles) > floor(t n_split / n_tiles));
+                             // workgroup w of a split tile stages and reduces the chunks J with J % 2 == w.
+                             // The grid holds n_tiles + n_split workgroups
   // batch launch (nullptr otherwise)
   const BatchJob* bjobs;       // job table
   const int32_t* bgroup_jobs;  // [bng] jobs of this launch

@@ -374,14 +374,25 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
   // element scales a_e, row 1 + o: the weights s_e of output o)
   __shared__ int sexp[SCALED ? (NOUT + 1) * kTile : 1];
 
-  // with nsplit > 1 a tile has nsplit workgroups (consecutive virtual ids, so
-  // the same XCD): all run the recursion, workgroup wpart stages and reduces
-  // the chunks J with J % nsplit == wpart -- shorter waves for grids too small
-  // to fill the chip, bitwise the same sums
-  const int ns = (args.nsplit > 1) ? args.nsplit : 1;
-  const int64_t vb = xcd_tile(blockIdx.x, n_tiles * ns);
-  const int64_t tile = vb / ns;
-  const int wpart = (int)(vb % ns);
+  // a split tile has two workgroups (consecutive virtual ids, so the same
+  // XCD): both run the recursion, workgroup wpart stages and reduces the chunks
+  // J with J % 2 == wpart -- shorter waves where the grid is too small to fill
+  // the chip, bitwise the same sums.  Split tiles are spread evenly: tile t's
+  // first virtual id is t + floor(t S / n_tiles) (S = n_split), and t is split
+  // iff the next one is two further on.
+  const int64_t S = args.n_split;
+  const int64_t vb = xcd_tile(blockIdx.x, n_tiles + S);
+  int64_t tile = vb;
+  int wpart = 0, ns = 1;
+  if (S > 0) {  // uniform; the host splits tiles only in launches of at most 2,048 tiles (32-bit products)
+    const uint32_t n = (uint32_t)n_tiles, s2 = (uint32_t)S, v = (uint32_t)vb;
+    uint32_t t = v * n / (n + s2);  // within one of the answer
+    while (t + 1 < n && (t + 1) + (t + 1) * s2 / n <= v) ++t;
+    while (t > 0 && t + t * s2 / n > v) --t;
+    tile = t;
+    wpart = (int)(v - (t + t * s2 / n));
+    ns = ((t + 1) * s2 / n > t * s2 / n) ? 2 : 1;
+  }
   const int lane = threadIdx.x;
   TileArgs a = args;
   int64_t q0 = tile * kTile;   // first sorted position of the tile
