@@ -172,6 +172,7 @@ q2x_status run(int kind, const double* verts, int64_t n_verts, const int32_t* el
   a.p = p;
   a.norm = norm;
   a.accumulate = (flags & Q2X_ACCUMULATE) ? 1 : 0;
+  a.count_bad_ids = (flags & Q2X_PRESORTED) ? 1 : 0;
   const int64_t n_tiles = (n_elems + kTile - 1) / kTile;
   // small grids leave the chip latency-bound: there two workgroups share a
   // tile's chunks (each runs the recursion).  Measured: FP64 gains with every

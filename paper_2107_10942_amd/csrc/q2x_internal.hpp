@@ -62,6 +62,7 @@ struct TileArgs {
   int p;                     // requested order (<= template P)
   int norm;
   int accumulate;
+  int count_bad_ids;         // presorted input (no bucketing pass): count ids outside [0, n_boxes) here
   int64_t n_split;           // tiles that get two workgroups (0 <= n_split <= n_tiles <= 2048 when > 0; spread evenly:
                              // tile t is split iff floor((t+1) n_split / n_tiles) > floor(t n_split / n_tiles));
                              // workgroup w of a split tile stages and reduces the chunks J with J % 2 == w.

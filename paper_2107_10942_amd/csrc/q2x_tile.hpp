@@ -439,7 +439,9 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
 
   // ---- element, box and FP64 geometry (Sec. 3.1, Eqs. (8)-(9); Sec. 3.3, Eq. (21))
   const int key = in_range ? (int)(a.keys[q] - key_off) : INT32_MIN;
-  const bool box_ok = in_range && key >= 0 && key < a.n_boxes;  // (bad ids were counted by the bucketing)
+  // ids outside [0, B) were counted by the bucketing, or are counted below
+  // when the caller presorted the input
+  const bool box_ok = in_range && key >= 0 && key < a.n_boxes;
   const int64_t e = in_range ? (a.perm ? (int64_t)a.perm[q] - elem_off : q) : 0;
   double sigma[NOUT];
 #pragma unroll
@@ -478,11 +480,12 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
   // ---- status (one atomic per wavefront and counter)
   {
     const uint64_t deg_mask = __ballot(degenerate);
-    const uint64_t skip_mask = __ballot(box_ok && !ok);
+    const uint64_t skip_mask = __ballot((box_ok && !ok) || (a.count_bad_ids && in_range && !box_ok));
     uint32_t fall = 0;
 #pragma unroll
     for (int b = 0; b < 5; ++b)
       if (__ballot((flag >> b) & 1u)) fall |= (1u << b);
+    if (a.count_bad_ids && __ballot(in_range && !box_ok)) fall |= Q2X_FLAG_BAD_BOX;
     if (lane == 0 && wpart == 0) {
       if (deg_mask) atomicAdd(&a.status->n_degenerate, (unsigned long long)__popcll(deg_mask));
       if (skip_mask) atomicAdd(&a.status->n_skipped, (unsigned long long)__popcll(skip_mask));

@@ -127,6 +127,54 @@ def test_presorted_and_repeat_are_bitwise_identical(prec):
     assert np.array_equal(F1, F3)
 
 
+@pytest.mark.parametrize("prec", [FP64, FP32_MIXED])
+@pytest.mark.parametrize("kind", [0, 4])
+def test_presorted_bad_ids_are_counted(kind, prec):
+    """Q2X_PRESORTED skips the bucketing, so the recursion kernel itself counts
+    the ids outside [0, B): non-decreasing ids that start with -1 and end with
+    ids >= B set Q2X_FLAG_BAD_BOX, count every such element as skipped, and the
+    valid elements give the oracle's coefficients."""
+    import torch
+    from paper_2107_10942_amd import q2x
+    from q2x_inputs import configs, octree
+    base = small_job(0, 700, 25, 9, seed=31)
+    order = np.argsort(base.elem_box, kind="stable")
+    eb = base.elem_box[order].astype(np.int32)
+    eb[:70] = -1          # more than one tile of ids below the range
+    eb[-45:] = 25         # one past the last box ...
+    eb[-5:] = 40          # ... and further out
+    n_bad = 70 + 45
+    bx = octree.Boxes(level=0, lo=-1, half=1, h=0.25, elem_box=eb, center=base.box_center,
+                      radius=base.box_radius, morton=base.boxes.morton, counts=None)
+    job = configs.Job(name="presorted_bad", kind=0, p=9, verts=base.verts, elems=base.elems[order],
+                      density=base.density[order], boxes=bx)
+    keep = (eb >= 0) & (eb < 25)
+    bk = octree.Boxes(level=0, lo=-1, half=1, h=0.25, elem_box=eb[keep], center=base.box_center,
+                      radius=base.box_radius, morton=base.boxes.morton, counts=None)
+    jk = configs.Job(name="valid", kind=0, p=9, verts=base.verts, elems=job.elems[keep], density=job.density[keep],
+                     boxes=bk)
+    R = oracle_ref(jk)
+    A = scale(jk)
+    if kind == 0:
+        F, st = run_gpu(job, prec, presorted=True)
+        outs = [(F, R, A)]
+    else:  # both layers in one call (the double layer takes a second density)
+        d2 = np.random.default_rng(3).uniform(-1, 1, job.n_elems)
+        v, e, d, ebt, bc, br = q2x.job_tensors(job)
+        ws = q2x.alloc_workspace(q2x.TRI_BOTH, job.n_elems, job.n_boxes, 9, prec)
+        o1, o2 = q2x.tri_both(v, e, d, torch.as_tensor(d2).cuda(), ebt, bc, br, 9, precision=prec, presorted=True,
+                              workspace=ws)
+        st = q2x.status(ws)
+        jd = configs.Job(name="valid_d", kind=1, p=9, verts=base.verts, elems=job.elems[keep], density=d2[keep],
+                         boxes=bk)
+        c = lambda t: t.cpu().numpy()[..., 0] + 1j * t.cpu().numpy()[..., 1]  # noqa: E731
+        outs = [(c(o1), R, A), (c(o2), oracle_ref(jd), scale(jd))]
+    assert st[0] == q2x.FLAG_BAD_BOX, st
+    assert st[2] == n_bad, st
+    for F, Rr, Ar in outs:
+        _check(F, Rr, Ar, 9, prec, f"presorted bad ids kind={kind} prec={prec}")
+
+
 @pytest.mark.parametrize("kind", KINDS)
 def test_moment_normalisation(kind):
     job = small_job(kind, 300, 12, 9, seed=21)
