@@ -67,7 +67,8 @@ typedef enum {
   Q2X_ERR_P_RANGE = -2,     /* p < 0 or p > Q2X_P_MAX */
   Q2X_ERR_WORKSPACE = -3,   /* workspace too small or misaligned */
   Q2X_ERR_HIP = -4,         /* a HIP runtime call failed */
-  Q2X_ERR_UNSUPPORTED = -5  /* valid request this build does not implement */
+  Q2X_ERR_UNSUPPORTED = -5, /* valid request this build does not implement */
+  Q2X_ERR_TOO_LARGE = -6    /* q2x_tri_both_noalloc: the call does not fit its static scratch */
 } q2x_status;
 
 typedef enum {
@@ -143,6 +144,34 @@ q2x_status q2x_tri_both(const double* verts, int64_t n_verts, const int32_t* tri
                         const double* box_center, const double* box_radius, int64_t n_boxes, int p,
                         int precision, int norm, unsigned flags, double* coeffs_single, double* coeffs_double,
                         void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * q2x_tri_both for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same computation and results (bitwise) without a workspace argument.
+ *   status   caller-owned device buffer of 64 bytes (8-byte aligned) that
+ *            receives the call's status block; read it with
+ *            q2x_status_get(status, stream, ...)
+ * The scratch memory (sort buffers, box start table, partial sums of boxes
+ * cut by tile edges) is a static device array of Q2X_NOALLOC_SCRATCH_BYTES
+ * bytes, one per GPU, loaded with the library's code and held until the
+ * process ends.  A call that needs more, i.e. when
+ * q2x_workspace_bytes(Q2X_TRI_BOTH, n_tris, n_boxes, p, precision) exceeds
+ * Q2X_NOALLOC_SCRATCH_BYTES (about 390,000 triangles at p = 16, one box per 12), returns
+ * Q2X_ERR_TOO_LARGE without doing anything.  The call makes no hipMalloc,
+ * hipFree or other allocation and no kernel timing; the first call on a
+ * device looks up the array's device address (hipGetSymbolAddress).
+ * Every call on one GPU shares that GPU's array (it keeps the previous call's
+ * contents; nothing in it needs to start at zero): calls that overlap in
+ * time on one GPU race, so order them on one stream.  Other arguments and
+ * errors as for q2x_tri_both.
+ */
+#define Q2X_NOALLOC_SCRATCH_BYTES (64u << 20)
+q2x_status q2x_tri_both_noalloc(const double* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+                                const double* density_single, const double* density_double,
+                                const int32_t* elem_box, const double* box_center, const double* box_radius,
+                                int64_t n_boxes, int p, int precision, int norm, unsigned flags,
+                                double* coeffs_single, double* coeffs_double, void* status, void* stream);
 
 /*
  * Line segments with constant scalar line density (the integrals K of Sec. 2,

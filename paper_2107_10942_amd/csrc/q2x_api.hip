@@ -93,10 +93,14 @@ bool get_ev(Prof::Ev& e) {
 
 // One call.  Output o (o < outputs of the kind) takes its density from
 // dens[o][e * dstride] and writes outs[o].
+// ext_status: the status block lives there instead of at the head of the
+// workspace (whose first slot is then unused); allow_timing: the call may
+// take part in kernel timing (which can create HIP events).
 q2x_status run(int kind, const double* verts, int64_t n_verts, const int32_t* elems, int64_t n_elems,
                const double* const* dens, int dstride, const int32_t* elem_box, const double* box_center,
                const double* box_radius, int64_t n_boxes, int p, int prec, int norm, unsigned flags,
-               double* const* outs, void* workspace, size_t workspace_bytes, void* stream) {
+               double* const* outs, void* workspace, size_t workspace_bytes, void* stream,
+               Status* ext_status = nullptr, bool allow_timing = true) {
   const int nout = outputs_per_kind(kind);
   if (p < 0 || p > Q2X_P_MAX) return Q2X_ERR_P_RANGE;
   if (n_verts < 0 || n_elems < 0 || n_boxes < 0 || n_elems >= ((int64_t)1 << 31) - 64 ||
@@ -128,7 +132,7 @@ q2x_status run(int kind, const double* verts, int64_t n_verts, const int32_t* el
 
   hipStream_t s = (hipStream_t)stream;
   char* ws = (char*)workspace;
-  Status* st = (Status*)(ws + L.status);
+  Status* st = ext_status ? ext_status : (Status*)(ws + L.status);
   int32_t* box_start = (int32_t*)(ws + L.box_start);
   int32_t* sort_scratch = (int32_t*)(ws + L.sort);
   double* partials = (double*)(ws + L.partials);
@@ -136,7 +140,7 @@ q2x_status run(int kind, const double* verts, int64_t n_verts, const int32_t* el
   Prof& PR = prof();
   Prof::Ev ev{};
   bool timing = false;
-  {
+  if (allow_timing) {
     std::lock_guard<std::mutex> g(PR.mu);
     timing = PR.on && get_ev(ev);
   }
@@ -221,6 +225,30 @@ q2x_status run(int kind, const double* verts, int64_t n_verts, const int32_t* el
   return Q2X_OK;
 }
 
+// ---- scratch of the entry point that allocates nothing (q2x_tri_both_noalloc)
+// One array per GPU, loaded with the code object and held until the process
+// ends.  In host code `scratch` only names the symbol: its device address
+// comes from hipGetSymbolAddress, once per device, with that device current.
+constexpr size_t kNoAllocBytes = (size_t)Q2X_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (nullptr on failure).
+void* scratch_of_current_device() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
 }  // namespace
 }  // namespace q2x
 
@@ -261,6 +289,28 @@ q2x_status q2x_tri_both(const double* verts, int64_t n_verts, const int32_t* tri
   double* outs[2] = {coeffs_single, coeffs_double};
   return run(Q2X_TRI_BOTH, verts, n_verts, tris, n_tris, dens, 1, elem_box, box_center, box_radius, n_boxes, p,
              precision, norm, flags, outs, workspace, workspace_bytes, stream);
+}
+
+q2x_status q2x_tri_both_noalloc(const double* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+                                const double* density_single, const double* density_double, const int32_t* elem_box,
+                                const double* box_center, const double* box_radius, int64_t n_boxes, int p,
+                                int precision, int norm, unsigned flags, double* coeffs_single,
+                                double* coeffs_double, void* status, void* stream) {
+  if (!status || ((uintptr_t)status % 8) != 0) return Q2X_ERR_ARG;
+  if (p < 0 || p > Q2X_P_MAX) return Q2X_ERR_P_RANGE;
+  if (n_tris < 0 || n_boxes < 0) return Q2X_ERR_ARG;
+  if (precision != Q2X_FP64 && precision != Q2X_FP32_MIXED) return Q2X_ERR_ARG;
+  const int P = bucket_order(p);
+  if (P < 0) return Q2X_ERR_UNSUPPORTED;
+  if (n_tris >= ((int64_t)1 << 31) - 64 || n_boxes >= ((int64_t)1 << 31) - 1) return Q2X_ERR_ARG;
+  // the scratch holds the workspace of q2x_tri_both (its status slot unused)
+  if (layout(n_tris, n_boxes, P, 2).total > kNoAllocBytes) return Q2X_ERR_TOO_LARGE;
+  void* ws = scratch_of_current_device();
+  if (!ws) return Q2X_ERR_HIP;
+  const double* dens[2] = {density_single, density_double};
+  double* outs[2] = {coeffs_single, coeffs_double};
+  return run(Q2X_TRI_BOTH, verts, n_verts, tris, n_tris, dens, 1, elem_box, box_center, box_radius, n_boxes, p,
+             precision, norm, flags, outs, ws, kNoAllocBytes, stream, (Status*)status, false);
 }
 
 q2x_status q2x_segment_vec(const double* verts, int64_t n_verts, const int32_t* segs, int64_t n_segs,
@@ -443,6 +493,9 @@ const char* q2x_status_string(int status) {
     case Q2X_ERR_WORKSPACE: return "Q2X_ERR_WORKSPACE: workspace missing, misaligned or too small";
     case Q2X_ERR_HIP: return "Q2X_ERR_HIP: HIP runtime error";
     case Q2X_ERR_UNSUPPORTED: return "Q2X_ERR_UNSUPPORTED";
+    case Q2X_ERR_TOO_LARGE:
+      return "Q2X_ERR_TOO_LARGE: the call needs more scratch than the no-allocation entry point holds "
+             "(Q2X_NOALLOC_SCRATCH_BYTES per GPU)";
     default: return "unknown q2x_status";
   }
 }

@@ -25,7 +25,7 @@ ACCUMULATE, PRESORTED = 1, 2
 P_MAX = 32
 FLAG_BAD_BOX, FLAG_NONFINITE, FLAG_RESERVED, FLAG_BAD_VERTEX, FLAG_NOT_SORTED = 1, 2, 4, 8, 16
 EXPORTS = ("q2x_workspace_bytes", "q2x_bucket_workspace_bytes", "q2x_bucket", "q2x_tri_single", "q2x_tri_double", "q2x_segment", "q2x_tet",
-           "q2x_tri_both", "q2x_segment_vec", "q2x_status_get", "q2x_status_string", "q2x_profile_enable", "q2x_profile_reset",
+           "q2x_tri_both", "q2x_tri_both_noalloc", "q2x_segment_vec", "q2x_status_get", "q2x_status_string", "q2x_profile_enable", "q2x_profile_reset",
            "q2x_profile_read", "q2x_version", "q2x_batch_plan", "q2x_batch_workspace_bytes", "q2x_batch_run", "q2x_batch_launch",
            "q2x_batch_job_status", "q2x_batch_groups", "q2x_batch_mode", "q2x_batch_destroy",
            "q2x_eval_workspace_bytes", "q2x_eval", "q2x_m2m_workspace_bytes", "q2x_m2m",
@@ -64,6 +64,9 @@ def lib():
             f.restype = ci
         L.q2x_tri_both.argtypes = [vp, i64, vp, i64, vp, vp, vp, vp, vp, i64, ci, ci, ci, cu, vp, vp, vp, sz, vp]
         L.q2x_tri_both.restype = ci
+        L.q2x_tri_both_noalloc.argtypes = [vp, i64, vp, i64, vp, vp, vp, vp, vp, i64, ci, ci, ci, cu, vp, vp, vp,
+                                           vp]
+        L.q2x_tri_both_noalloc.restype = ci
         L.q2x_segment_vec.argtypes = [vp, i64, vp, i64, vp, vp, vp, vp, i64, ci, ci, ci, cu, vp, vp, sz, vp]
         L.q2x_segment_vec.restype = ci
         L.q2x_bucket_workspace_bytes.argtypes = [i64, i64]
@@ -224,6 +227,41 @@ def tri_both(verts, tris, density_single, density_double, elem_box, box_center, 
                             _ptr(out_single, torch.float64, "out_single"),
                             _ptr(out_double, torch.float64, "out_double"),
                             ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream(stream))
+    _check(rc)
+    return out_single, out_double
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+STATUS_BYTES = 64
+
+
+def tri_both_noalloc(verts, tris, density_single, density_double, elem_box, box_center, box_radius, p, status,
+                     precision=FP32_MIXED, norm=NORM_FMM, accumulate=False, presorted=False, out_single=None,
+                     out_double=None, stream=None):
+    """tri_both without a workspace (q2x_tri_both_noalloc): the library's static
+    per-GPU scratch is used; `status` is a caller-owned 64-byte device buffer
+    (e.g. torch.empty(64, dtype=torch.uint8)) that receives the status block
+    (read it with status(status)).  Returns (out_single, out_double)."""
+    n_el = int(tris.shape[0]) if tris is not None else 0
+    nb = int(box_center.shape[0])
+    if tris is not None and tris.dim() == 2 and tris.shape[1] != 3:
+        raise Q2XError("triangles need 3 vertices")
+    if status is None or not status.is_cuda or status.numel() * status.element_size() < STATUS_BYTES:
+        raise Q2XError("status must be a device buffer of at least 64 bytes")
+    out_single = _out(out_single, nb, p, verts.device, "out_single")
+    out_double = _out(out_double, nb, p, verts.device, "out_double")
+    flags = (ACCUMULATE if accumulate else 0) | (PRESORTED if presorted else 0)
+    rc = lib().q2x_tri_both_noalloc(_ptr(verts, torch.float64, "verts"), int(verts.shape[0]),
+                                    _ptr(tris, torch.int32, "tris"), n_el,
+                                    _ptr(density_single, torch.float64, "density_single"),
+                                    _ptr(density_double, torch.float64, "density_double"),
+                                    _ptr(elem_box, torch.int32, "elem_box"),
+                                    _ptr(box_center, torch.float64, "box_center"),
+                                    _ptr(box_radius, torch.float64, "box_radius"),
+                                    nb, int(p), int(precision), int(norm), flags,
+                                    _ptr(out_single, torch.float64, "out_single"),
+                                    _ptr(out_double, torch.float64, "out_double"),
+                                    ctypes.c_void_p(status.data_ptr()), _stream(stream))
     _check(rc)
     return out_single, out_double
 
