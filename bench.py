@@ -161,18 +161,19 @@ def other_workloads(dev, reps=20):
             q2x.profile_enable(False)
             k = job.kind
             kern = rec_ms[k] / calls[k]
-            fl = flops.launch_flops(k, job.p, job.n_elems)
+            fl = flops.scope_launch_flops(k, job.p, job.n_elems)
             # binding roof: min(VALU peak, arithmetic intensity x HBM peak)
             by = flops.launch_bytes(k, job.p, job.n_elems, job.n_boxes)
             ai = fl / by
-            hbm_bound = ai < flops.PEAK_VALU_TFLOPS * 1e12 / (flops.PEAK_HBM_GBS * 1e9)
+            vpk = flops.peak_valu_tflops(prec == q2x.FP32_MIXED)
+            hbm_bound = ai < vpk * 1e12 / (flops.PEAK_HBM_GBS * 1e9)
             ach_tf = fl / (kern * 1e-3) / 1e12
             ach_gbs = by / (kern * 1e-3) / 1e9
             res[pn] = {"call_ms": dt * 1e3, "kernel_ms": kern,
                        "coefficients_per_s": job.n_elems * (job.p + 1) ** 2 / dt,
                        "kernel_tflops": ach_tf, "kernel_gbs": ach_gbs, "flop_per_byte": ai,
                        "bound": "hbm" if hbm_bound else "alu",
-                       "frac": (ach_gbs / flops.PEAK_HBM_GBS) if hbm_bound else (ach_tf / flops.PEAK_VALU_TFLOPS)}
+                       "frac": (ach_gbs / flops.PEAK_HBM_GBS) if hbm_bound else (ach_tf / vpk)}
         out[name] = res
     # the random walks again with a vector density (walk tangent x strength): three outputs, one recursion
     import numpy as np
@@ -222,24 +223,65 @@ def serving_workload(dev, n_requests, warmup=50, pool_size=24):
         for i in range(n):
             m = int(r.integers(0, len(meshes)))
             out.append(serving.Request(kind=int(r.integers(0, 2)), p=int(r.integers(8, 25)), arrival=float(arr[i]),
-                                       **meshes[m]))
+                                       mesh_id=m, **meshes[m]))
         return out
 
-    srv = serving.Server(dev, hbm_budget=budget, max_batch=16, p_fp32_max=32)
-    srv.serve(requests(20, 0, 1))  # warm-up (library load, allocator)
-    # capacity: a burst of requests all present at t = 0
-    burst = srv.serve(requests(120, 0, 2))
-    capacity = len(burst) / max(r.done for r in burst)
     out = {"workload": f"{pool_size} perturbed geodesic spheres ({sum(j.n_elems for j in pool)} triangles in all), "
                        f"N log-uniform [10k, 2M], p uniform [8, 24], single/double; requests draw a mesh, p and kind",
-           "hbm_budget_bytes": budget, "capacity_requests_per_s": capacity,
-           "p_fp32_max": 32, "p_fp32_max_basis": "FP32-mixed meets the 1e-5 scale-aware bar up to p = 32 "
-                                                 "in the parity tests, so no request falls back to FP64"}
-    for load in (0.5, 0.7, 0.9):
-        reqs = srv.serve(requests(warmup + n_requests, load * capacity, 10 + int(10 * load)))[warmup:]
-        summ = serving.latency_summary(reqs)
-        summ["batches"] = srv.stats["batches"]
-        out[f"load_{load}"] = summ
+           "hbm_budget_bytes": budget, "p_fp32_max": 32,
+           "p_fp32_max_basis": "FP32-mixed meets the 1e-5 scale-aware bar up to p = 32 in the parity tests, "
+                               "so no request falls back to FP64"}
+    for resident, name in ((True, "resident_meshes"), (False, "upload_per_request")):
+        srv = serving.Server(dev, hbm_budget=budget, max_batch=16, p_fp32_max=32, resident=resident,
+                             compute_streams=2)
+        srv.serve(requests(20, 0, 1))  # warm-up (library load, allocator; fills the resident cache)
+        # capacity: a burst of requests all present at t = 0
+        burst = srv.serve(requests(120, 0, 2))
+        capacity = len(burst) / max(r.done for r in burst)
+        res = {"capacity_requests_per_s": capacity, "compute_streams": 2}
+        for load in (0.5, 0.7, 0.9):
+            reqs = srv.serve(requests(warmup + n_requests, load * capacity, 10 + int(10 * load)))[warmup:]
+            summ = serving.latency_summary(reqs)
+            summ.update({k: srv.stats[k] for k in ("batches", "uploads", "resident_hits")})
+            res[f"load_{load}"] = summ
+        out[name] = res
+        del srv
+        torch.cuda.synchronize()
+    return out
+
+
+def cpu_other_workloads(nthr, seconds):
+    """The oracle's rate (element-coefficients/s) on the other workloads: the
+    1,280-triangle icosphere (p = 8) in full; the Kuhn tetrahedra and the
+    random-walk segments (p = 12) on every k-th box, k sized from a first run
+    on every 400th box so that each takes about `seconds`."""
+    import numpy as np
+
+    import oracle
+    from q2x_inputs import configs
+    out = {}
+    sm = configs.sphere_small()
+    t0 = time.perf_counter()
+    oracle.q2x(sm.kind, sm.p, sm.verts, sm.elems, sm.density, sm.elem_box, sm.box_center)
+    dt = time.perf_counter() - t0
+    out["icosphere_k3_1280_p8_single"] = {"value": sm.n_elems * (sm.p + 1) ** 2 / dt, "unit": "coefficients/s",
+                                          "cores": nthr, "kind": "oracle",
+                                          "sample": f"all {sm.n_boxes} boxes, {sm.n_elems} triangles, {dt:.3f} s"}
+    for name, job in (("kuhn_tets_511104_p12", configs.kuhn_tet_volume()),
+                      ("random_walk_segments_1000000_p12", configs.random_filaments())):
+        def sample(stride):
+            bx = np.arange(0, job.n_boxes, stride)
+            keep = np.isin(job.elem_box, bx)
+            t0 = time.perf_counter()
+            oracle.q2x(job.kind, job.p, job.verts, job.elems[keep], job.density[keep], job.elem_box[keep],
+                       job.box_center, boxes=bx)
+            return int(keep.sum()), time.perf_counter() - t0, len(bx)
+        ne, dt, nbx = sample(400)
+        stride = max(1, int(math.ceil(job.n_elems / max(ne / dt * seconds, 1.0))))
+        if stride < 400:
+            ne, dt, nbx = sample(stride)
+        out[name] = {"value": ne * (job.p + 1) ** 2 / dt, "unit": "coefficients/s", "cores": nthr, "kind": "oracle",
+                     "sample": f"every {stride}th box ({nbx} boxes, {ne} elements), {dt:.1f} s"}
     return out
 
 
@@ -465,9 +507,12 @@ def main():
         per_kind = {}
         for k in ws:
             avg = rec_ms[k] / max(calls[k], 1)
-            fl = flops.launch_flops(k, p, N)
+            fl = flops.scope_launch_flops(k, p, N)
+            fl_lean = flops.launch_flops(k, p, N)
             per_kind[q2x.KIND_NAMES[k]] = {"recursion_kernel_ms": avg, "call_ms": call_ms[k] / max(calls[k], 1),
-                                           "algorithmic_flops": fl, "tflops": fl / (avg * 1e-3) / 1e12}
+                                           "algorithmic_flops": fl, "tflops": fl / (avg * 1e-3) / 1e12,
+                                           "algorithmic_flops_lean": fl_lean,
+                                           "tflops_lean": fl_lean / (avg * 1e-3) / 1e12}
         return {"ms_per_step": ms, "value": coefs / (ms * 1e-3), "per_kind": per_kind, "flags": flags,
                 "single": coef_complex(outs[0]), "double": coef_complex(outs[1])}
 
@@ -489,12 +534,32 @@ def main():
 
     dom_name = max(mixed["per_kind"], key=lambda k: mixed["per_kind"][k]["recursion_kernel_ms"])
     dom = mixed["per_kind"][dom_name]
-    peak = flops.PEAK_VALU_TFLOPS
+    peak = flops.PEAK_FP32_TFLOPS
+    peak64 = flops.PEAK_FP64_TFLOPS
     traffic = stored_traffic("q2x_tile_kernel_tri_both_p16_perturbed_sphere_81920_traffic.md", libbuild.source_hash())
     roof = {"bound": "alu", "kernel": f"q2x_tile_kernel<16,{dom_name},float>", "achieved": dom["tflops"],
             "peak": peak, "unit": "TFLOP/s", "frac": dom["tflops"] / peak, "traffic": traffic,
             "launch_ms": dom["recursion_kernel_ms"], "flops_per_launch": dom["algorithmic_flops"],
+            "flop_model": "recursion of Eqs. (50)-(56) as written (complex products with xi, eta at 8 FLOPs), "
+                          "plus 4 FLOPs per output coefficient for the FP64 weight and box sum",
+            "achieved_lean": dom["tflops_lean"], "frac_lean": dom["tflops_lean"] / peak,
+            "flops_per_launch_lean": dom["algorithmic_flops_lean"],
+            "flop_model_lean": "operation-by-operation count using the conjugate pair xi, eta "
+                               "(paper_2107_10942_amd/flops.py element_flops)",
             "algorithmic_bytes_per_launch": flops.launch_bytes(q2x.TRI_BOTH, p, N, B)}
+    fp64_dom = plain["per_kind"][dom_name]
+
+    # the GPU's own peaks, measured (the published ones are the roofline's denominators)
+    buf = torch.empty(1 << 31, dtype=torch.uint8, device=dev)
+    mp = {"fp64_fma_tflops": q2x.peak_measure(q2x.PEAK_FMA64, buf)[0],
+          "fp32_fma_tflops": q2x.peak_measure(q2x.PEAK_FMA32, buf)[0],
+          "hbm_copy_gbs": q2x.peak_measure(q2x.PEAK_HBM_COPY, buf)[0],
+          "method": "q2x_peak_measure: 8 independent FMA chains per lane on 16 waves per SIMD (FP32 non-packed); "
+                    "a 1 GiB float4 copy (read + written bytes)"}
+    del buf
+    roof["frac_of_measured_peak"] = dom["tflops"] / mp["fp32_fma_tflops"]
+    roof["peak_basis"] = ("published FP32 vector peak; plain (non-packed) FP32 FMA issues at twice the FP64 rate on "
+                          "this GPU (measured_peaks.fp32_fma_tflops)")
 
     line = {
         "metric": "Q2X coefficients/s at p=16, FP32-mixed vs FP64 plain; serving p50/p99 latency",
@@ -506,7 +571,11 @@ def main():
                                "octree level 5, single+double layer, p=16",
                    "n_elements": N, "n_boxes": B, "p": p, "elements_per_step": 2 * N,
                    "coefficients_per_step": 2 * N * (p + 1) ** 2, "precision": "FP32-mixed"},
-        "fp64_plain": {"value": plain["value"], "ms_per_step": plain["ms_per_step"], "per_kind": plain["per_kind"]},
+        "fp64_value": plain["value"], "fp64_ms_per_step": plain["ms_per_step"],
+        "fp64_plain": {"value": plain["value"], "ms_per_step": plain["ms_per_step"], "per_kind": plain["per_kind"],
+                       "kernel_peak_tflops": peak64, "kernel_frac": fp64_dom["tflops"] / peak64,
+                       "kernel_frac_lean": fp64_dom["tflops_lean"] / peak64},
+        "kernel_speedup_mixed_vs_fp64": fp64_dom["recursion_kernel_ms"] / dom["recursion_kernel_ms"],
         "separate_calls": {"fp32_mixed_ms_per_step": separate[q2x.FP32_MIXED]["ms_per_step"],
                            "fp64_ms_per_step": separate[q2x.FP64]["ms_per_step"],
                            "per_kind_mixed": separate[q2x.FP32_MIXED]["per_kind"]},
@@ -518,6 +587,7 @@ def main():
         "mixed_vs_fp64_max_rel_diff": agree,
         "status_flags": {"mixed": mixed["flags"], "fp64": plain["flags"]},
         "roofline": roof,
+        "measured_peaks": mp,
     }
 
     if not args.no_large:
@@ -545,11 +615,14 @@ def main():
             q2x.profile_enable(False)
             k = big.kind
             avg = rec_ms[k] / calls[k]
-            fl = flops.launch_flops(k, big.p, big.n_elems)
+            vpk = flops.peak_valu_tflops(prec == q2x.FP32_MIXED)
+            fl = flops.scope_launch_flops(k, big.p, big.n_elems)
+            fl_lean = flops.launch_flops(k, big.p, big.n_elems)
             lg["fp32_mixed" if prec == q2x.FP32_MIXED else "fp64"] = {
                 "recursion_kernel_ms": avg, "call_ms": call_ms[k] / calls[k],
                 "coefficients_per_s": big.n_elems * (big.p + 1) ** 2 / ((t1 - t0) / reps),
-                "tflops": fl / (avg * 1e-3) / 1e12, "frac_of_valu_peak": fl / (avg * 1e-3) / 1e12 / peak}
+                "tflops": fl / (avg * 1e-3) / 1e12, "frac_of_valu_peak": fl / (avg * 1e-3) / 1e12 / vpk,
+                "frac_of_valu_peak_lean": fl_lean / (avg * 1e-3) / 1e12 / vpk}
         line["large_workload"] = {"workload": f"icosphere k=8, {big.n_elems} triangles, level 7, "
                                               f"{big.n_boxes} boxes, single layer, p=16", **lg}
 
@@ -597,6 +670,7 @@ def main():
                 table[f"{name}_{layer}"] = error_stats(res[layer][bx], refs[job.kind], en, job.density[keep],
                                                        job.elem_box[keep], bx, p)
         line["cpu_baseline"]["error_vs_oracle"] = table
+        line["cpu_baseline"]["other_workloads"] = cpu_other_workloads(nthr, args.cpu_seconds / 4)
         # the same oracle on one thread, on every 40th box (context for the all-core figure;
         # last, as the thread count it sets stays in force)
         bx1 = np.arange(0, B, 40)

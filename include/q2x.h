@@ -407,6 +407,20 @@ void q2x_profile_enable(int on);
 void q2x_profile_reset(void);
 q2x_status q2x_profile_read(double* recursion_ms, double* call_ms, int64_t* calls);
 
+/*
+ * Peak microbenchmarks of the running GPU (measurement aid; the measured
+ * denominators beside the published peaks of the roofline fractions).
+ *   which 0: FP64 FMA rate, 1: FP32 FMA rate (non-packed, as the library is
+ *   built), both in TFLOP/s; 2: HBM copy bandwidth in GB/s (bytes read +
+ *   written), copying the first half of `buffer` to the second.
+ *   buffer  device memory (256-byte aligned) the kernels may overwrite: at
+ *           least 2 MB for 0/1; for 2 the copy size is buffer_bytes / 2
+ *   reps    timed launches (after one warm-up); value: the rate; ms_per_rep:
+ *           the average launch time (may be NULL).  Synchronises `stream`.
+ */
+q2x_status q2x_peak_measure(int which, void* buffer, size_t buffer_bytes, int reps, void* stream, double* value,
+                            double* ms_per_rep);
+
 /* Library version string. */
 const char* q2x_version(void);
 

@@ -23,7 +23,8 @@ COMMON = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(HERE, "..", "include")]
 
-SIMPLE = ["q2x_api.hip", "q2x_bucket.hip", "q2x_dispatch.hip", "q2x_batch.hip", "q2x_m2m.hip", "q2x_near.hip"]
+SIMPLE = ["q2x_api.hip", "q2x_bucket.hip", "q2x_dispatch.hip", "q2x_batch.hip", "q2x_m2m.hip", "q2x_near.hip",
+          "q2x_peak.hip"]
 INST = [(k, f) for k in range(6) for f in (0, 1)]
 EVAL_INST = [(k, f) for k in range(4) for f in (0, 1)]
 

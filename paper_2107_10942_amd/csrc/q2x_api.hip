@@ -4,6 +4,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
@@ -11,13 +12,6 @@
 
 namespace q2x {
 
-hipError_t bucket_elements(const int32_t* elem_box, int64_t n, int64_t nb, int32_t* scratch, Status* status,
-                           hipStream_t s, const int32_t** keys_out, const int32_t** perm_out);
-hipError_t launch_box_bounds(const int32_t* keys, int64_t n, int64_t nb, int32_t* box_start, hipStream_t s,
-                             Status* order_check);
-hipError_t clear_status(Status* st, hipStream_t s);
-hipError_t copy_words(int32_t* dst, const int32_t* src, int64_t n, hipStream_t s);
-size_t bucket_scratch_bytes(int64_t n, int64_t nb);
 
 // Boxes whose elements span more than one tile: sum the per-tile partials in
 // tile order, finalise and store.  Empty boxes: zeros (unless accumulating).
@@ -28,7 +22,7 @@ __global__ __launch_bounds__(256) void q2x_fixup_kernel(FixupArgs f) {
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   for (int64_t b = wave; b < f.n_boxes; b += nwaves) {
     const int64_t s = f.n_pos ? f.box_start[b] : 0, t = f.n_pos ? f.box_start[b + 1] : 0;
-    fixup_box(lane, s, t, 0, 0, f.partials, f.outs, b, f.nout, f.p, f.P, f.norm, f.accumulate);
+    fixup_box(lane, s, t, 0, 0, f.te, f.partials, f.outs, b, f.nout, f.p, f.P, f.norm, f.accumulate);
   }
 }
 
@@ -39,10 +33,14 @@ size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
   size_t status, box_start, sort, partials, total;
+  int te;
+  int64_t n_tiles;
 };
 
-Layout layout(int64_t n, int64_t nb, int P, int nout) {
+Layout layout(int64_t n, int64_t nb, int P, int nout, int prec) {
   Layout L;
+  L.te = tile_width(n, prec);
+  L.n_tiles = (n + L.te - 1) / L.te;
   size_t off = 0;
   L.status = off;
   off += align_up(sizeof(Status));
@@ -51,8 +49,7 @@ Layout layout(int64_t n, int64_t nb, int P, int nout) {
   L.sort = off;
   off += align_up(bucket_scratch_bytes(n, nb));
   L.partials = off;
-  const int64_t ntiles = (n + kTile - 1) / kTile;
-  off += align_up((size_t)ntiles * 2 * (size_t)nout * (size_t)tri(P + 1) * 2 * sizeof(double));
+  off += align_up((size_t)L.n_tiles * 2 * (size_t)nout * (size_t)tri(P + 1) * 2 * sizeof(double));
   L.total = off;
   return L;
 }
@@ -127,7 +124,7 @@ q2x_status run(int kind, const double* verts, int64_t n_verts, const int32_t* el
   }
   const int P = bucket_order(p);
   if (P < 0) return Q2X_ERR_UNSUPPORTED;
-  const Layout L = layout(n_elems, n_boxes, P, nout);
+  const Layout L = layout(n_elems, n_boxes, P, nout, prec);
   if (workspace_bytes < L.total) return Q2X_ERR_WORKSPACE;
 
   hipStream_t s = (hipStream_t)stream;
@@ -177,7 +174,8 @@ q2x_status run(int kind, const double* verts, int64_t n_verts, const int32_t* el
   a.norm = norm;
   a.accumulate = (flags & Q2X_ACCUMULATE) ? 1 : 0;
   a.count_bad_ids = (flags & Q2X_PRESORTED) ? 1 : 0;
-  const int64_t n_tiles = (n_elems + kTile - 1) / kTile;
+  a.te = L.te;
+  const int64_t n_tiles = L.n_tiles;
   // small grids leave the chip latency-bound: there two workgroups share a
   // tile's chunks (each runs the recursion).  Measured: FP64 gains with every
   // tile split up to two tiles per SIMD (1,024 SIMDs); FP32, whose recursion
@@ -203,6 +201,7 @@ q2x_status run(int kind, const double* verts, int64_t n_verts, const int32_t* el
     f.box_start = box_start;
     f.partials = partials;
     f.n_pos = n_elems;
+    f.te = L.te;
     for (int o = 0; o < nout; ++o) f.outs[o] = outs[o];
     f.n_boxes = n_boxes;
     f.p = p;
@@ -261,7 +260,7 @@ size_t q2x_workspace_bytes(int kind, int64_t n_elems, int64_t n_boxes, int p, in
   if (precision != Q2X_FP64 && precision != Q2X_FP32_MIXED) return 0;
   const int P = bucket_order(p);
   if (P < 0) return 0;
-  return layout(n_elems, n_boxes, P, outputs_per_kind(kind)).total;
+  return layout(n_elems, n_boxes, P, outputs_per_kind(kind), precision).total;
 }
 
 #define Q2X_ENTRY(name, KIND)                                                                                      \
@@ -304,7 +303,7 @@ q2x_status q2x_tri_both_noalloc(const double* verts, int64_t n_verts, const int3
   if (P < 0) return Q2X_ERR_UNSUPPORTED;
   if (n_tris >= ((int64_t)1 << 31) - 64 || n_boxes >= ((int64_t)1 << 31) - 1) return Q2X_ERR_ARG;
   // the scratch holds the workspace of q2x_tri_both (its status slot unused)
-  if (layout(n_tris, n_boxes, P, 2).total > kNoAllocBytes) return Q2X_ERR_TOO_LARGE;
+  if (layout(n_tris, n_boxes, P, 2, precision).total > kNoAllocBytes) return Q2X_ERR_TOO_LARGE;
   void* ws = scratch_of_current_device();
   if (!ws) return Q2X_ERR_HIP;
   const double* dens[2] = {density_single, density_double};

@@ -29,11 +29,6 @@
 #include "q2x_internal.hpp"
 
 namespace q2x {
-hipError_t bucket_elements(const int32_t* elem_box, int64_t n, int64_t nb, int32_t* scratch, Status* status,
-                           hipStream_t s, const int32_t** keys_out, const int32_t** perm_out);
-hipError_t launch_box_bounds(const int32_t* keys, int64_t n, int64_t nb, int32_t* box_start, hipStream_t s,
-                             Status* order_check);
-size_t bucket_scratch_bytes(int64_t n, int64_t nb);
 
 namespace {
 
@@ -88,7 +83,8 @@ __global__ __launch_bounds__(256) void batch_fixup(const BatchJob* __restrict__ 
     }
     const BatchJob& J = jobs[lo];
     const int64_t b = gb - J.box_base;
-    fixup_box(lane, box_start[gb], box_start[gb + 1], box_start[J.box_base], J.tile_base, parts + J.part_off, J.outs,
+    fixup_box(lane, box_start[gb], box_start[gb + 1], box_start[J.box_base], J.tile_base, J.te, parts + J.part_off,
+              J.outs,
               b, J.nout, J.p, J.P, J.norm, J.accumulate);
   }
 }
@@ -315,8 +311,9 @@ q2x_status q2x_batch_plan(const q2x_job* jobs, int n_jobs, q2x_plan** out) {
     J.accumulate = (q.flags & Q2X_ACCUMULATE) ? 1 : 0;
     J.nout = G.nout;
     J.group = gidx[key];
+    J.te = tile_width(q.n_elems, q.precision);
     G.jobs.push_back(j);
-    G.tiles.push_back(G.tiles.back() + (q.n_elems + kTile - 1) / kTile);
+    G.tiles.push_back(G.tiles.back() + (q.n_elems + J.te - 1) / J.te);
   }
   P->n_total = P->elem_base[n_jobs];
   P->total_boxes = P->box_base[n_jobs];

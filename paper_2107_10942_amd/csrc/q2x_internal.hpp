@@ -63,6 +63,7 @@ struct TileArgs {
   int norm;
   int accumulate;
   int count_bad_ids;         // presorted input (no bucketing pass): count ids outside [0, n_boxes) here
+  int32_t te;                // elements per tile (1..64; tile t covers sorted positions [t te, (t + 1) te))
   int64_t n_split;           // tiles that get two workgroups (0 <= n_split <= n_tiles <= 2048 when > 0; spread evenly:
                              // tile t is split iff floor((t+1) n_split / n_tiles) > floor(t n_split / n_tiles));
                              // workgroup w of a split tile stages and reduces the chunks J with J % 2 == w.
@@ -90,7 +91,15 @@ struct BatchJob {
   int64_t tile_base;   // first tile of the job within its group's launch
   int64_t part_off;    // offset (doubles) of the job's group partials in the workspace
   int32_t kind, prec, P, p, norm, accumulate, nout, group, dstride;
+  int32_t te;          // elements per tile: the single call's (tile_width), so the sums are bitwise the same
 };
+
+// Elements per tile of a call: 64 (one per lane).  Narrower tiles that
+// spread a launch evenly over the wave slots (two FP32 / one FP64 wave per
+// SIMD) were measured on the 81,920-triangle sphere and gave nothing: the
+// launch time is set by the tiles with the most box segments (a flush per
+// segment and chunk), not by the number of tiles per SIMD.
+inline int tile_width(int64_t, int) { return kTile; }
 
 // Arguments of the receiving-side kernel (integrals of local expansions over
 // elements; one lane per element, no reduction).
@@ -140,6 +149,7 @@ struct FixupArgs {
   int nout;                  // outputs per element kind (1; 2 for Q2X_TRI_BOTH; 3 for Q2X_SEGMENT_VEC)
   int norm;
   int accumulate;
+  int te;                    // elements per tile of the recursion launch
 };
 
 // Logical tile of a workgroup: the hardware deals workgroups round-robin to
@@ -208,24 +218,14 @@ __device__ __forceinline__ void tri_nm(int g, int& n, int& m) {
   m = g - tri(nn);
 }
 
-// Sum the per-tile partials of box b (positions [s, t) of a sorted range
-// whose tiles start at position base; tiles numbered from tile0), finalise
-// and store.  Empty boxes get zeros unless accumulating.  One wavefront.
-__device__ __forceinline__ void fixup_box(int lane, int64_t s, int64_t t, int64_t base, int64_t tile0,
-                                          const double* partials, double* const* outs, int64_t b, int nout, int p,
-                                          int P, int norm, int accumulate) {
+// Box b spans tiles t0 < t1: sum its per-tile partial sums in tile order,
+// finalise and store.  Tile t0 left the raw sum of its last segment in slot 1,
+// every later tile that of its first segment in slot 0; a partial block is
+// [tile][slot][nout][tri(P+1)][2] doubles.  One wavefront.
+__device__ __forceinline__ void finish_cut_box(int lane, int64_t t0, int64_t t1, const double* partials,
+                                               double* out0, double* out1, double* out2, int64_t b, int nout, int p,
+                                               int P, int norm, int accumulate) {
   const int ncoef = (p + 1) * (p + 1);
-  auto row_of = [&](int o) { return outs[o] + b * (int64_t)ncoef * 2; };
-  if (t <= s) {
-    if (!accumulate)
-      for (int o = 0; o < nout; ++o) {
-        double* row = row_of(o);
-        for (int i = lane; i < 2 * ncoef; i += 64) row[i] = 0.0;
-      }
-    return;
-  }
-  const int64_t t0 = (s - base) / kTile, t1 = (t - 1 - base) / kTile;
-  if (t0 == t1) return;  // finished by the tile kernel
   const int nct_out = tri(p + 1);
   const int NCT = tri(P + 1);
   const int64_t pstride = (int64_t)nout * NCT;  // partial sums per (tile, slot)
@@ -234,21 +234,52 @@ __device__ __forceinline__ void fixup_box(int lane, int64_t s, int64_t t, int64_
     const int g = gg - o * nct_out;
     double ar = 0.0, ai = 0.0;
     for (int64_t tt = t0; tt <= t1; ++tt) {
-      const int slot = (tt == t0 && s != base + t0 * kTile) ? 1 : 0;
-      const double* pp = partials + (((tile0 + tt) * 2 + slot) * pstride + o * NCT + g) * 2;
+      const int slot = (tt == t0) ? 1 : 0;
+      cgdouble* pp = as_global(partials) + ((tt * 2 + slot) * pstride + o * NCT + g) * 2;
       ar += pp[0];
       ai += pp[1];
     }
     int n, m;
     tri_nm(g, n, m);
-    finalize_store(row_of(o), n, m, ar, ai, norm, accumulate);
+    double* const out = (o == 0) ? out0 : ((o == 1) ? out1 : out2);  // (selects: no indexed register array)
+    finalize_store(out + b * (int64_t)ncoef * 2, n, m, ar, ai, norm, accumulate);
   }
+}
+
+// Box b of a sorted range [s, t) whose tiles of te elements start at
+// position base (numbered from tile0 in `partials`): finish it if tile edges
+// cut it; empty boxes get zeros unless accumulating.  One wavefront.
+__device__ __forceinline__ void fixup_box(int lane, int64_t s, int64_t t, int64_t base, int64_t tile0, int te,
+                                          const double* partials, double* const* outs, int64_t b, int nout, int p,
+                                          int P, int norm, int accumulate) {
+  const int ncoef = (p + 1) * (p + 1);
+  if (t <= s) {
+    if (!accumulate)
+      for (int o = 0; o < nout; ++o) {
+        double* row = outs[o] + b * (int64_t)ncoef * 2;
+        for (int i = lane; i < 2 * ncoef; i += 64) row[i] = 0.0;
+      }
+    return;
+  }
+  const int64_t t0 = (s - base) / te, t1 = (t - 1 - base) / te;
+  if (t0 == t1) return;  // finished by the tile kernel
+  finish_cut_box(lane, tile0 + t0, tile0 + t1, partials, outs[0], nout > 1 ? outs[1] : nullptr,
+                 nout > 2 ? outs[2] : nullptr, b, nout, p, P, norm, accumulate);
 }
 
 }  // namespace q2x
 
 // Host-side launchers implemented in the per-kind translation units.
 namespace q2x {
+// bucketing (q2x_bucket.hip): sort elem_box -> (keys, perm); the first kernel
+// also clears the status block
+hipError_t bucket_elements(const int32_t* elem_box, int64_t n, int64_t nb, int32_t* scratch, Status* status,
+                           hipStream_t s, const int32_t** keys_out, const int32_t** perm_out);
+hipError_t launch_box_bounds(const int32_t* keys, int64_t n, int64_t nb, int32_t* box_start, hipStream_t s,
+                             Status* order_check);
+hipError_t clear_status(Status* st, hipStream_t s);
+hipError_t copy_words(int32_t* dst, const int32_t* src, int64_t n, hipStream_t s);
+size_t bucket_scratch_bytes(int64_t n, int64_t nb);
 hipError_t launch_tiles(int kind, int prec, int P, const TileArgs& a, int64_t n_tiles, hipStream_t s);
 int bucket_order(int p);  // smallest compiled bucket >= p (or -1)
 hipError_t launch_eval(int kind, int prec, int P, const EvalArgs& a, int64_t n_tiles, hipStream_t s);

@@ -213,7 +213,6 @@ __global__ __launch_bounds__(256) void q2x_near_kernel(NearArgs a) {
   }
 }
 
-hipError_t clear_status(Status* st, hipStream_t s);
 
 }  // namespace q2x
 

@@ -1,5 +1,5 @@
 // q2x_tile.hpp -- the Q2X recursion + box reduction kernel (one wavefront per
-// tile of 64 box-sorted elements, one lane per element).
+// tile of up to 64 box-sorted elements, one lane per element).
 //
 // Per lane: FP64 geometry of its element relative to its box centre, then the
 // m >= 0 ("tilde") recursions of Sec. 3.4, Eqs. (50)-(56), degree by degree,
@@ -350,6 +350,12 @@ __device__ __forceinline__ ElemGeom<NV, T> element_geometry(const double* verts,
   return g;
 }
 
+__device__ __forceinline__ int64_t readlane64(int64_t v, int i) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, i);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), i);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 template <int P, int KIND, typename T>
 __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t n_tiles) {
   using KI = KindInfo<KIND>;
@@ -395,7 +401,8 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
   }
   const int lane = threadIdx.x;
   TileArgs a = args;
-  int64_t q0 = tile * kTile;   // first sorted position of the tile
+  int te = a.te;               // elements per tile (uniform, 1..64; a batch job's own)
+  int64_t q0 = tile * te;      // first sorted position of the tile
   int64_t pos_end = a.n_pos;   // end of the sorted range the tile belongs to
   int64_t key_off = 0;         // sorted keys are key_off + box id
   int64_t elem_off = 0;        // the permutation holds elem_off + element index
@@ -429,11 +436,12 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
     key_off = J.box_base;
     const int64_t s0 = a.bbox_start[J.box_base];
     pos_end = a.bbox_start[J.box_base + J.n_boxes];
-    q0 = s0 + (tile - a.bgroup_tiles[lo]) * kTile;
+    te = J.te;
+    q0 = s0 + (tile - a.bgroup_tiles[lo]) * te;
     elem_off = J.elem_base;  // positions in the concatenation of all jobs
   }
   if (q0 >= pos_end) return;  // uniform (past the job's valid elements)
-  const int ne = (int)min<int64_t>(kTile, pos_end - q0);
+  const int ne = (int)min<int64_t>(te, pos_end - q0);
   const int64_t q = q0 + lane;
   const bool in_range = lane < ne;
 
@@ -467,6 +475,7 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
   // ---- box start table: box_start[b] = first position whose key >= b, keys
   // outside [0, B) counting as -1 / B (the fix-up kernel reads it)
   const int key_prev = (in_range && q > 0) ? (int)(a.keys[q - 1] - key_off) : INT32_MIN;
+  const int ncoef_out = (a.p + 1) * (a.p + 1);
   if (in_range && !batch && wpart == 0) {
     const int64_t nb = a.n_boxes;
     const int64_t kc = key < 0 ? -1 : (key >= nb ? nb : key);
@@ -494,12 +503,16 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
   }
 
   // ---- box boundaries inside the tile (uniform bit mask), open tile edges
-  const uint64_t bnd = __ballot(in_range && (lane == 0 || key != key_prev));
+  const bool seg_start = in_range && (lane == 0 || key != key_prev);
+  const uint64_t bnd = __ballot(seg_start);
+  const uint64_t vseg = __ballot(seg_start && box_ok);  // segments whose box is valid (flushed)
   bool head_open = false, tail_open = false;
   if (q0 > 0) head_open = (a.keys[q0 - 1] == a.keys[q0]);
-  if (ne == kTile && q0 + kTile < pos_end) tail_open = (a.keys[q0 + kTile] == a.keys[q0 + kTile - 1]);
+  if (ne == te && q0 + te < pos_end) tail_open = (a.keys[q0 + te] == a.keys[q0 + te - 1]);
   const int p = a.p;
-  const int ncoef_out = (p + 1) * (p + 1);
+  // offset (doubles) of the element's box row in an output, read by the
+  // reduction with readlane at segment starts
+  const int64_t row_off = box_ok ? (int64_t)key * ncoef_out * 2 : 0;
 
   // ---- weights of the staged values.  Output o of degree n of an element is
   // s_e a_e^(n - shift) G_n / (n + depth)!, G_n the recursion value (on Y =
@@ -554,7 +567,7 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
 
   // ---- reduction of chunk J (staged slots [J CMAX, J CMAX + CMAX))
   // Lane c + 32 h holds coefficient c of the chunk, real part (h = 0) or
-  // imaginary part (h = 1), and walks all 64 elements of the tile in order,
+  // imaginary part (h = 1), and walks the tile's elements in order,
   // summing the staged values in FP64 (elements at even and odd positions in
   // two partial sums, added where a box segment ends).  Box changes are
   // therefore the same for every lane; at each one the wave pairs the real and
@@ -598,9 +611,9 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
     double* const obase = ((NOUT == 1 || o == 0) ? a.outs[0] : (o == 1 ? a.outs[1] : a.outs[2])) + 2 * idx;
     double* const pbase = a.partials + (tile * 2 * (int64_t)(NOUT * NCT) + g_coef) * 2;
     const int nsh = (n > shift) ? n - shift : 0;
-    // segment state (uniform): first element, box id, scale exponents
+    // segment state (uniform): first element, box row offset, scale exponents
     int seg = 0;
-    int box = __builtin_amdgcn_readfirstlane(key);
+    int64_t boff = readlane64(row_off, 0);
     int eb = 0;
     int es[NOUT];
 #pragma unroll
@@ -617,7 +630,7 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
       else return (o == 0) ? es[0] : ((o == 1) ? es[1] : es[2]);
     };
     auto flush = [&](int sb, double t) Q2X_INLINE {
-      if (box < 0 || box >= a.n_boxes) return;  // uniform
+      if (!((vseg >> seg) & 1ull)) return;  // uniform: the segment's box id is outside [0, B)
       if constexpr (SCALED) t *= ldexp(invf, nsh * eb + es_of());
       // pair the halves: tr from lane c, ti from lane c + 32, on every lane
       const uint32_t lo = (uint32_t)__double2loint(t), hi = (uint32_t)__double2hiint(t);
@@ -625,9 +638,13 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
       const auto shi = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
       const double tr = __hiloint2double((int)shi[0], (int)slo[0]);
       const double ti = __hiloint2double((int)shi[1], (int)slo[1]);
-      if ((seg == 0 && head_open) || (sb == kTile && tail_open)) {  // uniform: box continues in another tile
+      // uniform: the box continues in another tile.  Its raw sum goes to slot
+      // 0 (the tile's first segment, continued from the previous tile) or
+      // slot 1 (the last segment, continued in the next tile)
+      const bool head = (seg == 0) && head_open;
+      if (head || (sb == ne && tail_open)) {
         if (h == 0 && live) {
-          gdouble* pp = as_global(pbase + ((seg == 0) ? 0 : (int64_t)(NOUT * NCT) * 2));
+          gdouble* pp = as_global(pbase + (head ? 0 : (int64_t)(NOUT * NCT) * 2));
           pp[0] = tr;
           pp[1] = ti;
         }
@@ -635,7 +652,7 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
       }
       if (!wr) return;
       double x = A1 * tr + A2 * ti, y = B1 * tr + B2 * ti;
-      gdouble* dst = as_global(obase + (int64_t)box * ncoef_out * 2);
+      gdouble* dst = as_global(obase + boff);
       if (a.accumulate) {
         x += dst[0];
         y += dst[1];
@@ -645,7 +662,7 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
     };
     auto next_segment = [&](int i) Q2X_INLINE {
       seg = i;
-      box = __builtin_amdgcn_readlane(key, i);
+      boff = readlane64(row_off, i);
       if constexpr (SCALED) {
         eb = __builtin_amdgcn_readlane(seg_eb, i);
 #pragma unroll
@@ -684,9 +701,10 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
     T cur[BATCH];
     load_half(IC<0>{}, 0, cur);
     load_half(IC<1>{}, 0, cur);
+    const int nwalk = (ne + BATCH - 1) & ~(BATCH - 1);  // the tile's elements (the rest of the batch adds zeros)
 #pragma unroll 1
-    for (int b0 = 0; b0 < kTile; b0 += BATCH) {  // uniform
-      const int bn = (b0 + BATCH < kTile) ? b0 + BATCH : b0;  // (last batch: a harmless reload)
+    for (int b0 = 0; b0 < nwalk; b0 += BATCH) {  // uniform
+      const int bn = (b0 + BATCH < nwalk) ? b0 + BATCH : b0;  // (last batch: a harmless reload)
       const uint32_t uc = (uint32_t)(cuts >> b0) & 0xffu;
       static_for<0, BATCH>([&](auto JB) Q2X_INLINE {
         constexpr int j = decltype(JB)::value;
@@ -863,6 +881,7 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
       reduce_body(K0, CJ, u / NOUT, o, k - ku, KI::shift(o), inv_factorial(u / NOUT + KI::depth(o)));
     }
   }
+
 }
 
 }  // namespace q2x

@@ -125,14 +125,55 @@ def m2m_child_flops(p: int) -> int:
     return 8 * macs + 10 * (p + 1) * (p + 2) // 2
 
 
-# MI355X vector-ALU peak.  256 CUs x 4 SIMDs x 16 lanes = 4096 FMA lanes per
-# clock at 2.4 GHz.  FP64 FMA issues at full rate: 4096 x 2 x 2.4e9 = 78.6
-# TFLOP/s.  Non-packed FP32 FMA issues at the same rate (78.6); the 157.3
-# TFLOP/s FP32 figure needs packed (two-wide) FP32 instructions, which this
-# library is built without.
+# A second, coarser count: the recursion of Eqs. (50)-(56) evaluated as
+# written, every complex product with xi or eta a full complex multiply-add
+# (8 FLOPs), zero padding pruned, FMA = 2.  Per element and order p it is a
+# quadratic in p (exact at p = 8, 12, 16, 20, 24):
+#   triangle single 32p^2 - 5p + 12, triangle double 41p^2 - 10p + 20,
+#   segment 21p^2 - 4p + 8, tetrahedron 43p^2 - 6p + 16
+# (2,020 / 4,560 / 8,124 / 12,712 / 18,324 for the single layer), plus
+# 4 (p+1)(p+2)/2 FLOPs per output for the FP64 weight and box sum.  The
+# single + double pass of one mesh shares the single layer's recursion to
+# degree p-1: single(p) + double(p) - single(p-1).  This is the count the
+# roofline's `achieved` uses; the leaner operation-by-operation model above
+# (which uses the conjugate pair xi, eta) is reported beside it.
+_SCOPE_QUAD = {TRI_SINGLE: (32, -5, 12), TRI_DOUBLE: (41, -10, 20), SEGMENT: (21, -4, 8), TET: (43, -6, 16)}
+
+
+def scope_recursion_flops(kind: int, p: int) -> int:
+    if kind == TRI_BOTH:
+        return scope_recursion_flops(TRI_SINGLE, p) + scope_recursion_flops(TRI_DOUBLE, p) - \
+            scope_recursion_flops(TRI_SINGLE, p - 1)
+    if kind == SEGMENT_VEC:
+        return scope_recursion_flops(SEGMENT, p)
+    a, b, c = _SCOPE_QUAD[kind]
+    return a * p * p + b * p + c if p > 0 else 0
+
+
+def scope_element_flops(kind: int, p: int) -> int:
+    nct = (p + 1) * (p + 2) // 2
+    return scope_recursion_flops(kind, p) + NOUT[kind] * 4 * nct
+
+
+def scope_launch_flops(kind: int, p: int, n_elems: int) -> int:
+    return scope_element_flops(kind, p) * n_elems
+
+
+# MI355X vector-ALU peaks.  256 CUs x 4 SIMDs x 16 lanes = 4096 FMA lanes per
+# clock at 2.4 GHz: FP64 FMA 4096 x 2 x 2.4e9 = 78.6 TFLOP/s.  FP32 FMA
+# issues at twice that rate even as plain (non-packed) v_fma_f32: a loop of
+# independent non-packed FP32 FMAs (q2x_peak_measure) reaches about 140
+# TFLOP/s, so FP32 work is priced against the published 157.3 TFLOP/s.
 CUS, LANES_PER_CU, CLOCK_HZ = 256, 64, 2.4e9
-PEAK_VALU_TFLOPS = CUS * LANES_PER_CU * 2 * CLOCK_HZ / 1e12  # 78.64
-PEAK_FP32_PACKED_TFLOPS = 2 * PEAK_VALU_TFLOPS                # 157.3 (not reachable here)
+PEAK_FP64_TFLOPS = CUS * LANES_PER_CU * 2 * CLOCK_HZ / 1e12  # 78.64
+PEAK_FP32_TFLOPS = 2 * PEAK_FP64_TFLOPS                      # 157.3
+
+
+def peak_valu_tflops(fp32: bool) -> float:
+    """Vector-ALU peak of the recursion's arithmetic type."""
+    return PEAK_FP32_TFLOPS if fp32 else PEAK_FP64_TFLOPS
+
+
 PEAK_HBM_GBS = 8000.0
 
 

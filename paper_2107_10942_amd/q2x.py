@@ -29,7 +29,7 @@ EXPORTS = ("q2x_workspace_bytes", "q2x_bucket_workspace_bytes", "q2x_bucket", "q
            "q2x_profile_read", "q2x_version", "q2x_batch_plan", "q2x_batch_workspace_bytes", "q2x_batch_run", "q2x_batch_launch",
            "q2x_batch_job_status", "q2x_batch_groups", "q2x_batch_mode", "q2x_batch_destroy",
            "q2x_eval_workspace_bytes", "q2x_eval", "q2x_m2m_workspace_bytes", "q2x_m2m",
-           "q2x_near_workspace_bytes", "q2x_near")
+           "q2x_near_workspace_bytes", "q2x_near", "q2x_peak_measure")
 
 
 class Q2XError(RuntimeError):
@@ -115,6 +115,9 @@ def lib():
         L.q2x_near_workspace_bytes.restype = sz
         L.q2x_near.argtypes = [vp, i64, vp, i64, vp, i64, vp, vp, i64, vp, vp, vp, vp, vp, cu, vp, sz, vp]
         L.q2x_near.restype = ci
+        L.q2x_peak_measure.argtypes = [ci, vp, sz, ci, vp, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_double)]
+        L.q2x_peak_measure.restype = ci
         _lib = L
     return _lib
 
@@ -551,6 +554,18 @@ def profile_read():
     d = (ctypes.c_int64 * N_KINDS)()
     _check(lib().q2x_profile_read(a, c, d))
     return list(a), list(c), list(d)
+
+
+PEAK_FMA64, PEAK_FMA32, PEAK_HBM_COPY = 0, 1, 2
+
+
+def peak_measure(which, buffer, reps=20, stream=None):
+    """Measured peak of the running GPU (q2x_peak_measure): (TFLOP/s or GB/s, ms per launch)."""
+    v = ctypes.c_double(0.0)
+    ms = ctypes.c_double(0.0)
+    _check(lib().q2x_peak_measure(int(which), ctypes.c_void_p(buffer.data_ptr()), buffer.numel() * buffer.element_size(),
+                                  int(reps), _stream(stream), ctypes.byref(v), ctypes.byref(ms)))
+    return v.value, ms.value
 
 
 def version():

@@ -152,3 +152,50 @@ def test_uneven_many_mesh_batch_reduced():
               sum(j.n_elems for j in jobs), flush=True)
         _compare(plan, specs, outs)
         plan.close()
+
+
+def test_batch_jobs_against_the_oracle():
+    """Every job of a mixed batch (all four element kinds and the fused single
+    + double layer, both precisions, orders inside and between the compiled
+    buckets) against the CPU oracle on a seeded sample of its boxes, to the
+    parity bar of its precision -- not only against the single calls."""
+    import torch
+    import metrics
+    from gpu_util import TOL, oracle_ref, scale, sample_boxes, sub_job
+    from paper_2107_10942_amd import q2x
+    from q2x_inputs import configs
+    plan_jobs = [(0, 2100, 60, 16, FP32_MIXED), (1, 900, 25, 9, FP64), (2, 1300, 30, 13, FP32_MIXED),
+                 (3, 700, 40, 12, FP64), (4, 1000, 33, 16, FP32_MIXED), (3, 500, 20, 20, FP32_MIXED),
+                 (1, 800, 30, 24, FP32_MIXED), (4, 600, 21, 8, FP64)]
+    jobs, specs = [], []
+    for i, (kind, n, nb, p, prec) in enumerate(plan_jobs):
+        job = small_job(kind if kind != 4 else 0, n, nb, p, seed=700 + i)
+        spec = _tensors(job)
+        spec["kind"] = kind
+        spec["precision"] = prec
+        d2 = None
+        if kind == 4:
+            d2 = np.random.default_rng(70 + i).uniform(-1, 1, job.n_elems)
+            spec["density2"] = torch.as_tensor(d2, dtype=torch.float64).cuda()
+        jobs.append((job, d2))
+        specs.append(spec)
+    plan = q2x.BatchPlan(specs)
+    outs = plan.run()
+    torch.cuda.synchronize()
+    for j, ((job, d2), spec) in enumerate(zip(jobs, specs)):
+        boxes = sample_boxes(job, 10, seed=j)
+        sub = sub_job(job, boxes)
+        layers = [(0 if spec["kind"] == 4 else spec["kind"], sub.density, outs[j][0] if spec["kind"] == 4 else outs[j])]
+        if spec["kind"] == 4:
+            keep = np.isin(job.elem_box, boxes)
+            layers.append((1, d2[keep], outs[j][1]))
+        for kind, dens, out in layers:
+            sj = configs.Job(name="s", kind=kind, p=job.p, verts=sub.verts, elems=sub.elems, density=dens,
+                             boxes=sub.boxes)
+            R = oracle_ref(sj, boxes=boxes)
+            A = scale(sj, boxes=boxes)
+            err = float(np.max(metrics.scale_aware_error(_c(out)[boxes], R, A, job.p)))
+            print(f"batch job {j} kind {kind} p {job.p} prec {spec['precision']} err {err:.2e}", flush=True)
+            assert err <= TOL[spec["precision"]], (j, kind, err)
+        assert plan.status(j)[0] == 0
+    plan.close()
