@@ -84,10 +84,20 @@ def batch_workload(dev, reps=5):
     for prec, name in ((q2x.FP32_MIXED, "fp32_mixed"), (q2x.FP64, "fp64")):
         specs = [dict(kind=j.kind, verts=t[0], elems=t[1], density=t[2], elem_box=t[3], box_center=t[4], p=j.p,
                       precision=prec) for j, t in zip(jobs, tens)]
+        # the default schedule (serial capture, no split tiles, one group per order bucket) ...
+        dplan = q2x.BatchPlan(specs)
+        dplan.set_schedule(0, 0, 0)
+        dplan.alloc_workspace(dev)
+        ms_default = timed(dplan.run, reps)
+        default_groups = dplan.groups
+        dplan.close()
+        # ... and the tuned one (the first run times the candidate schedules)
         plan = q2x.BatchPlan(specs)
         plan.alloc_workspace(dev)
+        t0 = time.perf_counter()
         plan.run()
         torch.cuda.synchronize()
+        tune_ms = (time.perf_counter() - t0) * 1e3
         ms_batch = timed(plan.run, reps)
         # the same jobs as single calls, one after the other (each with its own bucketing)
         wsz = max(q2x.workspace_bytes(j.kind, j.n_elems, j.n_boxes, j.p, prec) for j in jobs)
@@ -103,7 +113,10 @@ def batch_workload(dev, reps=5):
         results[name] = {"batch_ms": ms_batch, "sequential_ms": ms_seq, "batch_coefficients_per_s": coefs / (ms_batch * 1e-3),
                          "sequential_coefficients_per_s": coefs / (ms_seq * 1e-3), "speedup": ms_seq / ms_batch,
                          "batched_equals_sequential": bool(same), "groups": plan.groups,
-                         "capture": "parallel branches" if plan.mode == 1 else "serial"}
+                         "capture": "parallel branches" if plan.mode == 1 else "serial",
+                         "schedule": plan.schedule, "first_run_with_tuning_ms": tune_ms,
+                         "default_schedule": {"batch_ms": ms_default, "groups": default_groups},
+                         "tuned_vs_default_speedup": ms_default / ms_batch}
         plan.close()
         del seq_out
     out.update(results)

@@ -157,7 +157,7 @@ q2x_status q2x_tri_both(const double* verts, int64_t n_verts, const int32_t* tri
  * bytes, one per GPU, loaded with the library's code and held until the
  * process ends.  A call that needs more, i.e. when
  * q2x_workspace_bytes(Q2X_TRI_BOTH, n_tris, n_boxes, p, precision) exceeds
- * Q2X_NOALLOC_SCRATCH_BYTES (about 390,000 triangles at p = 16, one box per 12), returns
+ * Q2X_NOALLOC_SCRATCH_BYTES (about 200,000 triangles at p = 16, one box per 12), returns
  * Q2X_ERR_TOO_LARGE without doing anything.  The call makes no hipMalloc,
  * hipFree or other allocation and no kernel timing; the first call on a
  * device looks up the array's device address (hipGetSymbolAddress).
@@ -344,11 +344,12 @@ q2x_status q2x_near(const double* verts, int64_t n_verts, const int32_t* tris, i
  *                      buffer owned by the plan (allocated once, freed by
  *                      q2x_batch_destroy) and captures the launch sequence in
  *                      a HIP graph; later runs on that workspace replay it.
- *                      Without Q2X_ACCUMULATE jobs and with more than one
- *                      group, that first run times two captures (serial, or
- *                      group launches as parallel graph branches), keeps the
- *                      faster and synchronises `stream`.  Calls that share a
- *                      plan must be ordered on one stream.
+ *                      Unless a schedule was set or is cached for this
+ *                      device, library build and plan shape, and unless a job
+ *                      accumulates, that first run times the candidate
+ *                      schedules (q2x_schedule), keeps the fastest, caches it
+ *                      and synchronises `stream`.  Calls that share a plan
+ *                      must be ordered on one stream.
  *   q2x_batch_launch   enqueues the batch on `stream` directly, without a
  *                      graph and without any allocation: the job tables are
  *                      copied into the workspace on `stream` (for batches that
@@ -356,6 +357,30 @@ q2x_status q2x_near(const double* verts, int64_t n_verts, const int32_t* tris, i
  *   q2x_batch_job_status  q2x_status_get for one job of the last run.
  *   q2x_batch_groups / q2x_batch_mode  number of launch groups; chosen capture
  *                      (0 serial, 1 parallel branches, -1 not run yet).
+ *
+ * Schedules.  How a batch is launched never changes a bit of its results:
+ *   mode   0: group launches in one stream order; 1: parallel graph branches;
+ *   split  1: in groups of at most 2,048 tiles every tile gets two
+ *          workgroups, each staging every chunk and reducing half of them;
+ *   merge  a (kind, precision) order bucket whose jobs take at most `merge`
+ *          tiles runs in the next bucket up (0 never; INT_MAX: one group per
+ *          kind and precision);
+ *   tuned  (output only) 0 default, 1 chosen by timing or from the cache,
+ *          2 set by q2x_batch_set_schedule.
+ *   q2x_batch_get_schedule  the plan's current schedule.
+ *   q2x_batch_set_schedule  use `s` from now on (no tuning for this plan);
+ *                      Q2X_ERR_ARG for values out of range or a merge value
+ *                      whose layout needs more workspace than
+ *                      q2x_batch_workspace_bytes reported.
+ *   q2x_tune_cache_load / q2x_tune_cache_save  read / write the tuning cache
+ *                      as text, one line per entry: "device|build|shape",
+ *                      a tab, "mode split merge".  Entries of other devices
+ *                      or library builds are kept and never used.  When the
+ *                      environment variable Q2X_TUNE_CACHE names a file, it
+ *                      is read before the first lookup and every new tuning
+ *                      is appended to it.  Q2X_ERR_ARG if the file cannot be
+ *                      opened.
+ *   q2x_build_id       hash of the library's sources (part of the cache key).
  */
 typedef struct q2x_job {
   int kind, p, precision, norm;
@@ -382,6 +407,14 @@ q2x_status q2x_batch_job_status(const q2x_plan* plan, const void* workspace, int
 int q2x_batch_groups(const q2x_plan* plan);
 int q2x_batch_mode(const q2x_plan* plan);
 void q2x_batch_destroy(q2x_plan* plan);
+typedef struct q2x_schedule {
+  int32_t mode, split, merge, tuned;
+} q2x_schedule;
+q2x_status q2x_batch_get_schedule(const q2x_plan* plan, q2x_schedule* out);
+q2x_status q2x_batch_set_schedule(q2x_plan* plan, const q2x_schedule* s);
+q2x_status q2x_tune_cache_load(const char* path);
+q2x_status q2x_tune_cache_save(const char* path);
+const char* q2x_build_id(void);
 
 /*
  * Read the device status word of the last call that used `workspace`

@@ -55,6 +55,31 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def library_hash() -> str:
+    """Hash of every source of the library (its build identity, q2x_build_id)."""
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".hpp", ".cpp")))
+    for f in files:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    with open(os.path.join(HERE, "..", "include", "q2x.h"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _build_id_object(verbose) -> str:
+    """The build-identity unit, compiled with the host compiler on every build."""
+    obj = os.path.join(BUILD, "q2x_build_id.o")
+    cmd = [os.environ.get("CXX", "g++"), "-O2", "-fPIC", f'-DQ2X_BUILD_ID="{library_hash()}"', "-c",
+           os.path.join(CSRC, "q2x_build_id.cpp"), "-o", obj + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(obj + ".tmp", obj)
+    return obj
+
+
 def _headers():
     return [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".hpp")] + \
         [os.path.join(HERE, "..", "include", "q2x.h")]
@@ -65,6 +90,12 @@ def _stale(obj, srcs):
         return True
     t = os.path.getmtime(obj)
     return any(os.path.getmtime(s) > t for s in list(srcs) + _headers())
+
+
+def _build_id_stale(obj) -> bool:
+    t = os.path.getmtime(obj)
+    srcs = [os.path.join(CSRC, f) for f in os.listdir(CSRC)] + [os.path.join(HERE, "..", "include", "q2x.h")]
+    return any(os.path.getmtime(s) > t for s in srcs)
 
 
 def _compile(unit, verbose):
@@ -91,7 +122,12 @@ def build(force: bool = True, verbose: bool = False, jobs: int | None = None) ->
         with ThreadPoolExecutor(max_workers=jobs) as ex:
             list(ex.map(lambda u: _compile(u, verbose), todo))
     objs = [u[0] for u in units]
-    if todo or not os.path.exists(LIB):
+    bid = os.path.join(BUILD, "q2x_build_id.o")
+    fresh_id = not os.path.exists(bid) or _build_id_stale(bid)
+    if fresh_id:
+        _build_id_object(verbose)
+    objs.append(bid)
+    if todo or fresh_id or not os.path.exists(LIB):
         cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
         if verbose:
             print(" ".join(cmd), flush=True)

@@ -12,14 +12,27 @@
 // job's coefficients are bitwise those of the single call on that job.
 //
 // The sequence is captured once into a HIP graph (per workspace) and replayed.
-// Two captures are compared on the first run -- the group launches in one
-// stream order, or as parallel branches of the graph -- unless a job
-// accumulates into its output, and the faster is kept.
+// How it is launched is a schedule with three choices, none of which changes a
+// single bit of any result: the group launches in one stream order or as
+// parallel branches of the graph; two workgroups per tile in groups of at most
+// 2,048 tiles (each stages every chunk and reduces half of them, as in the
+// single calls on small grids); and small order buckets merged into the next
+// bucket up of the same (kind, precision) -- a job runs its own order p in a
+// kernel compiled for a larger P, with the same chunks and sums, in fewer
+// launches.  The first run of a plan on a workspace (no job accumulating)
+// times the candidate schedules and keeps the fastest; the choice is cached
+// per (device, library build, launch shapes) in memory, and in a text file
+// when the Q2X_TUNE_CACHE environment variable names one (read on first use,
+// appended after every new tuning) or q2x_tune_cache_load/save is called.
 #include <hip/hip_runtime.h>
 
 #include <string.h>
 
+#include <stdio.h>
+#include <stdlib.h>
+
 #include <algorithm>
+#include <climits>
 #include <map>
 #include <mutex>
 #include <string>
@@ -96,13 +109,74 @@ struct Group {
   int64_t part_off;            // doubles
 };
 
+// A launch schedule (see the top of this file).  merge: a bucket group of at
+// most `merge` tiles joins the next bucket up (0 never, INT_MAX always).
+struct Sched {
+  int mode = 0, split = 0, merge = 0;
+};
+
+// Everything that depends on the schedule: groups, job table, workspace layout.
+struct Layout {
+  std::vector<BatchJob> jobs;
+  std::vector<Group> groups;
+  size_t parts_doubles = 0;
+  std::vector<char> table;  // host image of the job tables
+  size_t t_jobs = 0, t_elem_base = 0, t_box_base = 0;
+  std::vector<size_t> t_gjobs, t_gtiles;
+  size_t off_table = 0, off_status = 0, off_keys = 0, off_sort = 0, off_box_start = 0, off_parts = 0, total = 0;
+};
+
 std::mutex& tune_mu() {
   static std::mutex m;
   return m;
 }
-std::map<std::string, int>& tune_cache() {  // plan signature -> capture mode
-  static std::map<std::string, int> c;
+// (device, library build, launch shapes) -> schedule
+std::map<std::string, Sched>& tune_cache() {
+  static std::map<std::string, Sched> c;
   return c;
+}
+
+bool parse_line(const std::string& line, std::string& key, Sched& s) {
+  const size_t t = line.find('\t');
+  if (t == std::string::npos || t == 0) return false;
+  key = line.substr(0, t);
+  return sscanf(line.c_str() + t + 1, "%d %d %d", &s.mode, &s.split, &s.merge) == 3 && (s.mode == 0 || s.mode == 1) &&
+         (s.split == 0 || s.split == 1) && s.merge >= 0;
+}
+
+int cache_load_locked(const char* path) {
+  FILE* f = fopen(path, "r");
+  if (!f) return -1;
+  char buf[4096];
+  int n = 0;
+  while (fgets(buf, sizeof(buf), f)) {
+    std::string line(buf);
+    while (!line.empty() && (line.back() == '\n' || line.back() == '\r')) line.pop_back();
+    std::string key;
+    Sched sc;
+    if (parse_line(line, key, sc)) {
+      tune_cache()[key] = sc;
+      ++n;
+    }
+  }
+  fclose(f);
+  return n;
+}
+
+// Q2X_TUNE_CACHE: read once, before the first lookup
+const char* env_cache_path_locked() {
+  static bool loaded = false;
+  const char* path = getenv("Q2X_TUNE_CACHE");
+  if (path && *path && !loaded) (void)cache_load_locked(path);
+  loaded = true;
+  return (path && *path) ? path : nullptr;
+}
+
+std::string device_key() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  return std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount);
 }
 
 }  // namespace
@@ -113,19 +187,19 @@ using namespace q2x;
 struct q2x_plan {
   int n_jobs = 0;
   bool any_accumulate = false;
-  std::vector<BatchJob> jobs;
+  std::vector<q2x_job> src;                  // the caller's jobs
   std::vector<int64_t> elem_base, box_base;  // size n_jobs + 1
-  std::vector<Group> groups;
   int64_t n_total = 0, total_boxes = 0;
-  size_t parts_doubles = 0;
-  // job tables: host image; q2x_batch_launch copies it into the workspace, the
-  // graph of q2x_batch_run reads a device copy owned by the plan
-  std::vector<char> table;
+  Sched sched;        // the schedule of `lay`
+  bool forced = false;  // set by the caller: never tuned
+  bool tuned = false;   // chosen by timing (here or from the cache)
+  Layout lay;
+  size_t ws_need = 0;     // workspace bytes: the largest layout of any candidate schedule
+  size_t table_need = 0;  // job table bytes: the largest of any candidate schedule
+  // the graph's device copy of the job tables, owned by the plan, allocated
+  // once (every graph of the plan reads it at the same address)
   char* dev_table = nullptr;
-  size_t t_jobs = 0, t_elem_base = 0, t_box_base = 0;  // offsets inside the table
-  std::vector<size_t> t_gjobs, t_gtiles;
-  // workspace layout
-  size_t off_table = 0, off_status = 0, off_keys = 0, off_sort = 0, off_box_start = 0, off_parts = 0, total = 0;
+  size_t dev_table_cap = 0;
   // graph capture (created on the first q2x_batch_run)
   hipStream_t cap[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<hipEvent_t> evs;
@@ -133,7 +207,7 @@ struct q2x_plan {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int mode = -1;
-  std::string signature;
+  std::string signature;  // launch shapes of the default grouping
 };
 
 namespace {
@@ -155,129 +229,73 @@ bool job_ok(const q2x_job& j) {
   return true;
 }
 
-// the launch sequence on stream s, job tables at tab (mode 1: group launches
-// on the capture streams as parallel branches)
-hipError_t enqueue(q2x_plan* P, char* ws, const char* tab, int mode, hipStream_t s) {
-  const BatchJob* d_jobs = (const BatchJob*)(tab + P->t_jobs);
-  const int64_t* d_elem_base = (const int64_t*)(tab + P->t_elem_base);
-  const int64_t* d_box_base = (const int64_t*)(tab + P->t_box_base);
-  Status* st = (Status*)(ws + P->off_status);
-  int32_t* keys = (int32_t*)(ws + P->off_keys);
-  int32_t* sort_scratch = (int32_t*)(ws + P->off_sort);
-  int32_t* box_start = (int32_t*)(ws + P->off_box_start);
-  double* parts = (double*)(ws + P->off_parts);
-  const int64_t n_words = (int64_t)(P->n_jobs + 1) * (int64_t)(sizeof(Status) / 4);
-  hipLaunchKernelGGL(batch_clear, dim3((unsigned)std::min<int64_t>((n_words + 255) / 256, 1024)), dim3(256), 0, s,
-                     (uint32_t*)st, n_words);
-  const int32_t* skeys = keys;
-  const int32_t* sperm = nullptr;
-  if (P->n_total > 0) {
-    const int64_t blocks = std::min<int64_t>((P->n_total + 255) / 256, 65536);
-    hipLaunchKernelGGL(batch_gather_keys, dim3((unsigned)blocks), dim3(256), 0, s, d_jobs, d_elem_base,
-                       P->n_jobs, P->n_total, P->total_boxes, keys, st);
-    // the sort's own status block (after the jobs') absorbs its invalid-key count
-    hipError_t e = bucket_elements(keys, P->n_total, P->total_boxes, sort_scratch, st + P->n_jobs, s, &skeys, &sperm);
-    if (e != hipSuccess) return e;
+int outputs_of(int kind) { return kind == Q2X_TRI_BOTH ? 2 : (kind == Q2X_SEGMENT_VEC ? 3 : 1); }
+
+// The bucket every job runs in under merge threshold `merge`: within one
+// (kind, precision), buckets in increasing order; a bucket whose jobs (with
+// those carried into it) take at most `merge` tiles carries them to the next
+// bucket present.
+std::vector<int> job_buckets(const q2x_plan* P, int merge) {
+  std::vector<int> b(P->n_jobs);
+  std::map<std::tuple<int, int, int>, std::vector<int>> by;  // (kind, prec, bucket) -> jobs
+  for (int j = 0; j < P->n_jobs; ++j) {
+    const q2x_job& q = P->src[j];
+    b[j] = bucket_order(q.p);
+    by[std::make_tuple(q.kind, q.precision, b[j])].push_back(j);
   }
-  hipError_t e = launch_box_bounds(skeys, P->n_total, P->total_boxes, box_start, s, nullptr);
-  if (e != hipSuccess) return e;
-  hipEvent_t* ev = P->evs.data();
-  const bool par = (mode == 1) && P->groups.size() > 1;
-  if (par) {
-    if (hipEventRecord(ev[0], s) != hipSuccess) return hipErrorUnknown;
+  std::vector<int> carry;
+  int ck = -1, cp = -1;
+  int64_t ctiles = 0;
+  for (auto& kv : by) {  // ordered by kind, precision, bucket
+    const int kind = std::get<0>(kv.first), prec = std::get<1>(kv.first), Pb = std::get<2>(kv.first);
+    if (kind != ck || prec != cp) {  // a new (kind, precision): nothing carried in
+      carry.clear();
+      ctiles = 0;
+      ck = kind;
+      cp = prec;
+    }
+    for (int j : carry) b[j] = Pb;
+    std::vector<int> here = carry;
+    int64_t tiles = ctiles;
+    for (int j : kv.second) {
+      here.push_back(j);
+      tiles += (P->src[j].n_elems + tile_width(P->src[j].n_elems, prec) - 1) / tile_width(P->src[j].n_elems, prec);
+    }
+    const auto nx = std::next(by.find(kv.first));
+    const bool last = nx == by.end() || std::get<0>(nx->first) != kind || std::get<1>(nx->first) != prec;
+    if (!last && tiles <= (int64_t)merge) {
+      carry = here;
+      ctiles = tiles;
+    } else {
+      carry.clear();
+      ctiles = 0;
+    }
   }
-  for (size_t g = 0; g < P->groups.size(); ++g) {
-    const Group& G = P->groups[g];
-    const int64_t n_tiles = G.tiles.back();
-    if (n_tiles == 0) continue;
-    hipStream_t gs = par ? P->cap[1 + g % 3] : s;
-    if (par && hipStreamWaitEvent(gs, ev[0], 0) != hipSuccess) return hipErrorUnknown;
-    TileArgs a{};
-    a.keys = skeys;
-    a.perm = sperm;
-    a.partials = parts + G.part_off;
-    a.bjobs = d_jobs;
-    a.bgroup_jobs = (const int32_t*)(tab + P->t_gjobs[g]);  // (tab: device memory)
-    a.bgroup_tiles = (const int64_t*)(tab + P->t_gtiles[g]);
-    a.bng = (int32_t)G.jobs.size();
-    a.bstatus = st;
-    a.bbox_start = box_start;
-    e = launch_tiles(G.kind, G.prec, G.P, a, n_tiles, gs);
-    if (e != hipSuccess) return e;
-    if (par && hipEventRecord(ev[1 + g], gs) != hipSuccess) return hipErrorUnknown;
-  }
-  if (par)
-    for (size_t g = 0; g < P->groups.size(); ++g)
-      if (P->groups[g].tiles.back() > 0 && hipStreamWaitEvent(s, ev[1 + g], 0) != hipSuccess) return hipErrorUnknown;
-  if (P->total_boxes > 0) {
-    const int64_t blocks = std::min<int64_t>((P->total_boxes + 3) / 4, 65536);
-    hipLaunchKernelGGL(batch_fixup, dim3((unsigned)blocks), dim3(256), 0, s, d_jobs, d_box_base, P->n_jobs,
-                       P->total_boxes, box_start, parts);
-  }
-  return hipGetLastError();
+  return b;
 }
 
-hipError_t capture(q2x_plan* P, char* ws, int mode, hipGraph_t* g, hipGraphExec_t* x) {
-  if (hipStreamBeginCapture(P->cap[0], hipStreamCaptureModeThreadLocal) != hipSuccess) return hipErrorUnknown;
-  const hipError_t e = enqueue(P, ws, P->dev_table, mode, P->cap[0]);
-  hipGraph_t graph = nullptr;
-  const hipError_t e2 = hipStreamEndCapture(P->cap[0], &graph);
-  if (e != hipSuccess || e2 != hipSuccess) {
-    if (graph) (void)hipGraphDestroy(graph);
-    return e != hipSuccess ? e : e2;
-  }
-  if (hipGraphInstantiate(x, graph, nullptr, nullptr, 0) != hipSuccess) {
-    (void)hipGraphDestroy(graph);
-    return hipErrorUnknown;
-  }
-  *g = graph;
-  return hipSuccess;
-}
-
-void drop_graph(q2x_plan* P) {
-  if (P->exec) (void)hipGraphExecDestroy(P->exec);
-  if (P->graph) (void)hipGraphDestroy(P->graph);
-  P->exec = nullptr;
-  P->graph = nullptr;
-  P->graph_ws = nullptr;
-}
-
-}  // namespace
-
-extern "C" {
-
-q2x_status q2x_batch_plan(const q2x_job* jobs, int n_jobs, q2x_plan** out) {
-  if (!out) return Q2X_ERR_ARG;
-  *out = nullptr;
-  if (!jobs || n_jobs <= 0) return Q2X_ERR_ARG;
-  for (int j = 0; j < n_jobs; ++j)
-    if (!job_ok(jobs[j])) return (jobs[j].p < 0 || jobs[j].p > Q2X_P_MAX) ? Q2X_ERR_P_RANGE : Q2X_ERR_ARG;
-  q2x_plan* P = new q2x_plan();
-  P->n_jobs = n_jobs;
-  P->jobs.resize(n_jobs);
-  P->elem_base.assign(n_jobs + 1, 0);
-  P->box_base.assign(n_jobs + 1, 0);
+void build_layout(const q2x_plan* P, const Sched& sc, Layout& L) {
+  L = Layout();
+  const std::vector<int> bk = job_buckets(P, sc.merge);
   std::map<std::tuple<int, int, int>, int> gidx;
-  for (int j = 0; j < n_jobs; ++j) {
-    const q2x_job& q = jobs[j];
-    P->elem_base[j + 1] = P->elem_base[j] + q.n_elems;
-    P->box_base[j + 1] = P->box_base[j] + q.n_boxes;
-    if (q.flags & Q2X_ACCUMULATE) P->any_accumulate = true;
-    const int Pb = bucket_order(q.p);
+  L.jobs.resize(P->n_jobs);
+  for (int j = 0; j < P->n_jobs; ++j) {
+    const q2x_job& q = P->src[j];
+    const int Pb = bk[j];
     const auto key = std::make_tuple(q.kind, q.precision, Pb);
     if (!gidx.count(key)) {
-      gidx[key] = (int)P->groups.size();
+      gidx[key] = (int)L.groups.size();
       Group G;
       G.kind = q.kind;
       G.prec = q.precision;
       G.P = Pb;
-      G.nout = (q.kind == Q2X_TRI_BOTH) ? 2 : (q.kind == Q2X_SEGMENT_VEC ? 3 : 1);
+      G.nout = outputs_of(q.kind);
       G.tiles.push_back(0);
       G.part_off = 0;
-      P->groups.push_back(G);
+      L.groups.push_back(G);
     }
-    Group& G = P->groups[gidx[key]];
-    BatchJob& J = P->jobs[j];
+    Group& G = L.groups[gidx[key]];
+    BatchJob& J = L.jobs[j];
     J = BatchJob{};
     J.verts = q.verts;
     J.elems = q.elems;
@@ -315,33 +333,27 @@ q2x_status q2x_batch_plan(const q2x_job* jobs, int n_jobs, q2x_plan** out) {
     G.jobs.push_back(j);
     G.tiles.push_back(G.tiles.back() + (q.n_elems + J.te - 1) / J.te);
   }
-  P->n_total = P->elem_base[n_jobs];
-  P->total_boxes = P->box_base[n_jobs];
-  if (P->n_total >= ((int64_t)1 << 31) - 64 || P->total_boxes >= ((int64_t)1 << 31) - 1) {
-    delete P;
-    return Q2X_ERR_ARG;
-  }
   size_t parts = 0;
-  for (Group& G : P->groups) {
+  for (Group& G : L.groups) {
     G.part_off = (int64_t)parts;
     parts += (size_t)G.tiles.back() * 2 * (size_t)G.nout * (size_t)tri(G.P + 1) * 2;
     parts = (parts + 31) & ~(size_t)31;  // 256-byte aligned group regions
   }
-  for (BatchJob& J : P->jobs) J.part_off = P->groups[J.group].part_off;
-  P->parts_doubles = parts;
+  for (BatchJob& J : L.jobs) J.part_off = L.groups[J.group].part_off;
+  L.parts_doubles = parts;
   // workspace layout (the job tables are appended below)
   size_t off = 0;
-  P->off_status = off;
-  off += align_up((size_t)(n_jobs + 1) * sizeof(Status));
-  P->off_keys = off;
+  L.off_status = off;
+  off += align_up((size_t)(P->n_jobs + 1) * sizeof(Status));
+  L.off_keys = off;
   off += align_up((size_t)P->n_total * sizeof(int32_t) + 4);
-  P->off_sort = off;
+  L.off_sort = off;
   off += align_up(bucket_scratch_bytes(P->n_total, P->total_boxes));
-  P->off_box_start = off;
+  L.off_box_start = off;
   off += align_up((size_t)(P->total_boxes + 1) * sizeof(int32_t));
-  P->off_parts = off;
+  L.off_parts = off;
   off += align_up(parts * sizeof(double) + 8);
-  P->total = off;
+  L.total = off;
   // job tables (host image)
   size_t tb = 0;
   auto reserve = [&](size_t n) {
@@ -349,132 +361,379 @@ q2x_status q2x_batch_plan(const q2x_job* jobs, int n_jobs, q2x_plan** out) {
     tb += align_up(n);
     return o;
   };
-  P->t_jobs = reserve(sizeof(BatchJob) * n_jobs);
-  P->t_elem_base = reserve(sizeof(int64_t) * (n_jobs + 1));
-  P->t_box_base = reserve(sizeof(int64_t) * (n_jobs + 1));
-  for (const Group& G : P->groups) {
-    P->t_gjobs.push_back(reserve(sizeof(int32_t) * G.jobs.size()));
-    P->t_gtiles.push_back(reserve(sizeof(int64_t) * G.tiles.size()));
+  L.t_jobs = reserve(sizeof(BatchJob) * P->n_jobs);
+  L.t_elem_base = reserve(sizeof(int64_t) * (P->n_jobs + 1));
+  L.t_box_base = reserve(sizeof(int64_t) * (P->n_jobs + 1));
+  for (const Group& G : L.groups) {
+    L.t_gjobs.push_back(reserve(sizeof(int32_t) * G.jobs.size()));
+    L.t_gtiles.push_back(reserve(sizeof(int64_t) * G.tiles.size()));
   }
-  P->table.assign(tb, 0);
-  memcpy(P->table.data() + P->t_jobs, P->jobs.data(), sizeof(BatchJob) * n_jobs);
-  memcpy(P->table.data() + P->t_elem_base, P->elem_base.data(), sizeof(int64_t) * (n_jobs + 1));
-  memcpy(P->table.data() + P->t_box_base, P->box_base.data(), sizeof(int64_t) * (n_jobs + 1));
-  for (size_t g = 0; g < P->groups.size(); ++g) {
-    const Group& G = P->groups[g];
-    memcpy(P->table.data() + P->t_gjobs[g], G.jobs.data(), sizeof(int32_t) * G.jobs.size());
-    memcpy(P->table.data() + P->t_gtiles[g], G.tiles.data(), sizeof(int64_t) * G.tiles.size());
+  L.table.assign(tb, 0);
+  memcpy(L.table.data() + L.t_jobs, L.jobs.data(), sizeof(BatchJob) * P->n_jobs);
+  memcpy(L.table.data() + L.t_elem_base, P->elem_base.data(), sizeof(int64_t) * (P->n_jobs + 1));
+  memcpy(L.table.data() + L.t_box_base, P->box_base.data(), sizeof(int64_t) * (P->n_jobs + 1));
+  for (size_t g = 0; g < L.groups.size(); ++g) {
+    const Group& G = L.groups[g];
+    memcpy(L.table.data() + L.t_gjobs[g], G.jobs.data(), sizeof(int32_t) * G.jobs.size());
+    memcpy(L.table.data() + L.t_gtiles[g], G.tiles.data(), sizeof(int64_t) * G.tiles.size());
   }
-  P->off_table = P->total;
-  P->total += align_up(tb);
-  // signature of the launch shapes (autotune cache key)
+  L.off_table = L.total;
+  L.total += align_up(tb);
+}
+
+// The candidate schedules the tuner times (distinct layouts only matter for
+// merge; mode 1 only with more than one group).
+std::vector<Sched> candidates(const q2x_plan* P) {
+  std::vector<Sched> out;
+  std::vector<std::vector<int>> seen;
+  for (int merge : {0, 1024, INT_MAX}) {
+    const std::vector<int> b = job_buckets(P, merge);
+    if (std::find(seen.begin(), seen.end(), b) != seen.end()) continue;
+    seen.push_back(b);
+    std::map<std::tuple<int, int, int>, int> g;
+    for (int j = 0; j < P->n_jobs; ++j) g[std::make_tuple(P->src[j].kind, P->src[j].precision, b[j])] = 1;
+    for (int split = 0; split < 2; ++split)
+      for (int mode = 0; mode < (g.size() > 1 ? 2 : 1); ++mode) {
+        Sched s;
+        s.mode = mode;
+        s.split = split;
+        s.merge = merge;
+        out.push_back(s);
+      }
+  }
+  return out;
+}
+
+std::string cache_key(const q2x_plan* P) { return device_key() + "|" + q2x_build_id() + "|" + P->signature; }
+
+// the launch sequence on stream s, job tables at tab (mode 1: group launches
+// on the capture streams as parallel branches)
+hipError_t enqueue(q2x_plan* P, char* ws, const char* tab, int mode, hipStream_t s) {
+  const Layout& L = P->lay;
+  const BatchJob* d_jobs = (const BatchJob*)(tab + L.t_jobs);
+  const int64_t* d_elem_base = (const int64_t*)(tab + L.t_elem_base);
+  const int64_t* d_box_base = (const int64_t*)(tab + L.t_box_base);
+  Status* st = (Status*)(ws + L.off_status);
+  int32_t* keys = (int32_t*)(ws + L.off_keys);
+  int32_t* sort_scratch = (int32_t*)(ws + L.off_sort);
+  int32_t* box_start = (int32_t*)(ws + L.off_box_start);
+  double* parts = (double*)(ws + L.off_parts);
+  const int64_t n_words = (int64_t)(P->n_jobs + 1) * (int64_t)(sizeof(Status) / 4);
+  hipLaunchKernelGGL(batch_clear, dim3((unsigned)std::min<int64_t>((n_words + 255) / 256, 1024)), dim3(256), 0, s,
+                     (uint32_t*)st, n_words);
+  const int32_t* skeys = keys;
+  const int32_t* sperm = nullptr;
+  if (P->n_total > 0) {
+    const int64_t blocks = std::min<int64_t>((P->n_total + 255) / 256, 65536);
+    hipLaunchKernelGGL(batch_gather_keys, dim3((unsigned)blocks), dim3(256), 0, s, d_jobs, d_elem_base,
+                       P->n_jobs, P->n_total, P->total_boxes, keys, st);
+    // the sort's own status block (after the jobs') absorbs its invalid-key count
+    hipError_t e = bucket_elements(keys, P->n_total, P->total_boxes, sort_scratch, st + P->n_jobs, s, &skeys, &sperm);
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = launch_box_bounds(skeys, P->n_total, P->total_boxes, box_start, s, nullptr);
+  if (e != hipSuccess) return e;
+  hipEvent_t* ev = P->evs.data();
+  const bool par = (mode == 1) && L.groups.size() > 1;
+  if (par) {
+    if (hipEventRecord(ev[0], s) != hipSuccess) return hipErrorUnknown;
+  }
+  for (size_t g = 0; g < L.groups.size(); ++g) {
+    const Group& G = L.groups[g];
+    const int64_t n_tiles = G.tiles.back();
+    if (n_tiles == 0) continue;
+    hipStream_t gs = par ? P->cap[1 + g % 3] : s;
+    if (par && hipStreamWaitEvent(gs, ev[0], 0) != hipSuccess) return hipErrorUnknown;
+    TileArgs a{};
+    a.keys = skeys;
+    a.perm = sperm;
+    a.partials = parts + G.part_off;
+    a.bjobs = d_jobs;
+    a.bgroup_jobs = (const int32_t*)(tab + L.t_gjobs[g]);  // (tab: device memory)
+    a.bgroup_tiles = (const int64_t*)(tab + L.t_gtiles[g]);
+    a.bng = (int32_t)G.jobs.size();
+    a.bstatus = st;
+    a.bbox_start = box_start;
+    a.n_split = (P->sched.split && n_tiles <= 2048) ? n_tiles : 0;  // every tile of a small group split
+    e = launch_tiles(G.kind, G.prec, G.P, a, n_tiles, gs);
+    if (e != hipSuccess) return e;
+    if (par && hipEventRecord(ev[1 + g], gs) != hipSuccess) return hipErrorUnknown;
+  }
+  if (par)
+    for (size_t g = 0; g < L.groups.size(); ++g)
+      if (L.groups[g].tiles.back() > 0 && hipStreamWaitEvent(s, ev[1 + g], 0) != hipSuccess) return hipErrorUnknown;
+  if (P->total_boxes > 0) {
+    const int64_t blocks = std::min<int64_t>((P->total_boxes + 3) / 4, 65536);
+    hipLaunchKernelGGL(batch_fixup, dim3((unsigned)blocks), dim3(256), 0, s, d_jobs, d_box_base, P->n_jobs,
+                       P->total_boxes, box_start, parts);
+  }
+  return hipGetLastError();
+}
+
+hipError_t capture(q2x_plan* P, char* ws, int mode, hipGraph_t* g, hipGraphExec_t* x) {
+  if (hipStreamBeginCapture(P->cap[0], hipStreamCaptureModeThreadLocal) != hipSuccess) return hipErrorUnknown;
+  const hipError_t e = enqueue(P, ws, P->dev_table, mode, P->cap[0]);
+  hipGraph_t graph = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(P->cap[0], &graph);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return e != hipSuccess ? e : e2;
+  }
+  if (hipGraphInstantiate(x, graph, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return hipErrorUnknown;
+  }
+  *g = graph;
+  return hipSuccess;
+}
+
+void drop_graph(q2x_plan* P) {
+  if (P->exec) (void)hipGraphExecDestroy(P->exec);
+  if (P->graph) (void)hipGraphDestroy(P->graph);
+  P->exec = nullptr;
+  P->graph = nullptr;
+  P->graph_ws = nullptr;
+}
+
+// make `sc` the plan's schedule (layout rebuilt; any captured graph dropped)
+void set_sched(q2x_plan* P, const Sched& sc) {
+  drop_graph(P);
+  P->sched = sc;
+  build_layout(P, sc, P->lay);
+}
+
+// the plan's device job table <- the current layout's (synchronous).  The
+// buffer is allocated once, at its largest size, so graphs captured under
+// other schedules keep a valid address.
+bool upload_table(q2x_plan* P) {
+  const size_t n = P->lay.table.size();
+  if (!P->dev_table) {
+    const size_t cap = std::max(P->table_need, n);
+    if (hipMalloc((void**)&P->dev_table, cap) != hipSuccess) return false;
+    P->dev_table_cap = cap;
+  }
+  if (n > P->dev_table_cap) return false;
+  return hipMemcpy(P->dev_table, P->lay.table.data(), n, hipMemcpyHostToDevice) == hipSuccess;
+}
+
+bool ensure_streams(q2x_plan* P) {
+  if (P->cap[0]) return true;
+  bool ok = true;
+  for (int i = 0; i < 4 && ok; ++i) ok = hipStreamCreateWithFlags(&P->cap[i], hipStreamNonBlocking) == hipSuccess;
+  // one event per group of the finest layout (no merging) + the fork
+  std::map<std::tuple<int, int, int>, int> g;
+  for (const q2x_job& q : P->src) g[std::make_tuple(q.kind, q.precision, bucket_order(q.p))] = 1;
+  P->evs.resize(g.size() + 1, nullptr);
+  for (auto& e : P->evs)
+    if (ok) ok = hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+  return ok;
+}
+
+}  // namespace
+
+extern "C" {
+
+q2x_status q2x_batch_plan(const q2x_job* jobs, int n_jobs, q2x_plan** out) {
+  if (!out) return Q2X_ERR_ARG;
+  *out = nullptr;
+  if (!jobs || n_jobs <= 0) return Q2X_ERR_ARG;
+  for (int j = 0; j < n_jobs; ++j)
+    if (!job_ok(jobs[j])) return (jobs[j].p < 0 || jobs[j].p > Q2X_P_MAX) ? Q2X_ERR_P_RANGE : Q2X_ERR_ARG;
+  q2x_plan* P = new q2x_plan();
+  P->n_jobs = n_jobs;
+  P->src.assign(jobs, jobs + n_jobs);
+  P->elem_base.assign(n_jobs + 1, 0);
+  P->box_base.assign(n_jobs + 1, 0);
+  for (int j = 0; j < n_jobs; ++j) {
+    P->elem_base[j + 1] = P->elem_base[j] + jobs[j].n_elems;
+    P->box_base[j + 1] = P->box_base[j] + jobs[j].n_boxes;
+    if (jobs[j].flags & Q2X_ACCUMULATE) P->any_accumulate = true;
+  }
+  P->n_total = P->elem_base[n_jobs];
+  P->total_boxes = P->box_base[n_jobs];
+  if (P->n_total >= ((int64_t)1 << 31) - 64 || P->total_boxes >= ((int64_t)1 << 31) - 1) {
+    delete P;
+    return Q2X_ERR_ARG;
+  }
+  // the default schedule's layout; its launch shapes key the tuning cache
+  set_sched(P, Sched());
   std::string sig;
-  for (const Group& G : P->groups)
+  for (const Group& G : P->lay.groups)
     sig += std::to_string(G.kind) + "," + std::to_string(G.prec) + "," + std::to_string(G.P) + "," +
            std::to_string(G.tiles.back()) + ";";
   sig += std::to_string(P->n_total) + "/" + std::to_string(P->total_boxes);
   P->signature = sig;
+  // workspace and job table: enough for every candidate schedule's layout
+  P->ws_need = P->lay.total;
+  P->table_need = P->lay.table.size();
+  for (const Sched& c : candidates(P)) {
+    Layout L;
+    build_layout(P, c, L);
+    P->ws_need = std::max(P->ws_need, L.total);
+    P->table_need = std::max(P->table_need, L.table.size());
+  }
   *out = P;
   return Q2X_OK;
 }
 
-size_t q2x_batch_workspace_bytes(const q2x_plan* plan) { return plan ? plan->total : 0; }
+size_t q2x_batch_workspace_bytes(const q2x_plan* plan) { return plan ? plan->ws_need : 0; }
 
-int q2x_batch_groups(const q2x_plan* plan) { return plan ? (int)plan->groups.size() : 0; }
+int q2x_batch_groups(const q2x_plan* plan) { return plan ? (int)plan->lay.groups.size() : 0; }
 
 int q2x_batch_mode(const q2x_plan* plan) { return plan ? plan->mode : -1; }
 
+q2x_status q2x_batch_get_schedule(const q2x_plan* plan, q2x_schedule* out) {
+  if (!plan || !out) return Q2X_ERR_ARG;
+  out->mode = plan->sched.mode;
+  out->split = plan->sched.split;
+  out->merge = plan->sched.merge;
+  out->tuned = plan->forced ? 2 : (plan->tuned ? 1 : 0);
+  return Q2X_OK;
+}
+
+q2x_status q2x_batch_set_schedule(q2x_plan* plan, const q2x_schedule* s) {
+  if (!plan || !s) return Q2X_ERR_ARG;
+  if ((s->mode != 0 && s->mode != 1) || (s->split != 0 && s->split != 1) || s->merge < 0) return Q2X_ERR_ARG;
+  Sched sc;
+  sc.mode = s->mode;
+  sc.split = s->split;
+  sc.merge = s->merge;
+  Layout L;
+  build_layout(plan, sc, L);
+  // (a threshold between the candidates' can need more workspace or table
+  // than the plan reported)
+  if (L.total > plan->ws_need || L.table.size() > plan->table_need) return Q2X_ERR_ARG;
+  set_sched(plan, sc);
+  plan->forced = true;
+  plan->tuned = false;
+  return Q2X_OK;
+}
+
 q2x_status q2x_batch_run(q2x_plan* plan, void* workspace, size_t workspace_bytes, void* stream) {
   if (!plan) return Q2X_ERR_ARG;
-  if (!workspace || ((uintptr_t)workspace % kAlign) != 0 || workspace_bytes < plan->total) return Q2X_ERR_WORKSPACE;
+  if (!workspace || ((uintptr_t)workspace % kAlign) != 0 || workspace_bytes < plan->ws_need) return Q2X_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   if (plan->exec && plan->graph_ws == workspace)
     return hipGraphLaunch(plan->exec, s) == hipSuccess ? Q2X_OK : Q2X_ERR_HIP;
   drop_graph(plan);
-  if (!plan->cap[0]) {
-    bool ok = true;
-    for (int i = 0; i < 4 && ok; ++i) ok = hipStreamCreateWithFlags(&plan->cap[i], hipStreamNonBlocking) == hipSuccess;
-    plan->evs.resize(plan->groups.size() + 1, nullptr);
-    for (auto& e : plan->evs)
-      if (ok) ok = hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
-    if (!ok) return Q2X_ERR_HIP;
-  }
-  if (!plan->dev_table) {  // the graph's job tables: a device copy owned by the plan
-    if (hipMalloc((void**)&plan->dev_table, plan->table.size()) != hipSuccess) return Q2X_ERR_HIP;
-    if (hipMemcpy(plan->dev_table, plan->table.data(), plan->table.size(), hipMemcpyHostToDevice) != hipSuccess)
-      return Q2X_ERR_HIP;
-  }
-  int mode = 0;
-  bool tuned = false;
-  {
+  if (!ensure_streams(plan)) return Q2X_ERR_HIP;
+  char* ws = (char*)workspace;
+  bool cached = false;
+  const char* cache_path = nullptr;
+  std::string key;
+  if (!plan->forced && !plan->tuned) {
+    key = cache_key(plan);
     std::lock_guard<std::mutex> g(tune_mu());
-    auto it = tune_cache().find(plan->signature);
+    cache_path = env_cache_path_locked();
+    auto it = tune_cache().find(key);
     if (it != tune_cache().end()) {
-      mode = it->second;
-      tuned = true;
+      Layout L;
+      build_layout(plan, it->second, L);
+      if (L.total <= plan->ws_need && L.table.size() <= plan->table_need) {
+        set_sched(plan, it->second);
+        plan->tuned = true;
+        cached = true;
+      }
     }
   }
-  char* ws = (char*)workspace;
-  if (!tuned && !plan->any_accumulate && plan->groups.size() > 1) {
-    // time both captures (each replay computes the full, idempotent result)
+  if (!plan->forced && !plan->tuned && !cached && !plan->any_accumulate) {
+    // time every candidate (each replay computes the full, idempotent and
+    // bitwise identical result; the last one leaves it in place)
+    const std::vector<Sched> cands = candidates(plan);
     float best = 0.f;
-    for (int m = 0; m < 2; ++m) {
+    int ibest = -1;
+    hipGraph_t bg = nullptr;
+    hipGraphExec_t bx = nullptr;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return Q2X_ERR_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      return Q2X_ERR_HIP;
+    }
+    q2x_status rc = Q2X_OK;
+    for (size_t i = 0; i < cands.size() && rc == Q2X_OK; ++i) {
+      set_sched(plan, cands[i]);
       hipGraph_t gr = nullptr;
       hipGraphExec_t ex = nullptr;
-      if (capture(plan, ws, m, &gr, &ex) != hipSuccess) return Q2X_ERR_HIP;
-      hipEvent_t e0, e1;
-      (void)hipEventCreate(&e0);
-      (void)hipEventCreate(&e1);
+      if (!upload_table(plan) || capture(plan, ws, cands[i].mode, &gr, &ex) != hipSuccess) {
+        rc = Q2X_ERR_HIP;
+        break;
+      }
       (void)hipGraphLaunch(ex, s);
       (void)hipEventRecord(e0, s);
       for (int r = 0; r < 2; ++r) (void)hipGraphLaunch(ex, s);
       (void)hipEventRecord(e1, s);
       float ms = 0.f;
-      const bool okt = hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
-      (void)hipEventDestroy(e0);
-      (void)hipEventDestroy(e1);
-      if (!okt) {
+      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
         (void)hipGraphExecDestroy(ex);
         (void)hipGraphDestroy(gr);
-        return Q2X_ERR_HIP;
+        rc = Q2X_ERR_HIP;
+        break;
       }
-      if (m == 0 || ms < best) {
-        drop_graph(plan);
+      if (ibest < 0 || ms < best) {
+        if (bx) (void)hipGraphExecDestroy(bx);
+        if (bg) (void)hipGraphDestroy(bg);
         best = ms;
-        plan->graph = gr;
-        plan->exec = ex;
-        plan->mode = m;
+        ibest = (int)i;
+        bg = gr;
+        bx = ex;
       } else {
         (void)hipGraphExecDestroy(ex);
         (void)hipGraphDestroy(gr);
       }
     }
-    std::lock_guard<std::mutex> g(tune_mu());
-    tune_cache()[plan->signature] = plan->mode;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != Q2X_OK) {
+      if (bx) (void)hipGraphExecDestroy(bx);
+      if (bg) (void)hipGraphDestroy(bg);
+      return rc;
+    }
+    // the best schedule's layout and job table back in place under its graph
+    set_sched(plan, cands[ibest]);
+    if (!upload_table(plan)) {
+      (void)hipGraphExecDestroy(bx);
+      (void)hipGraphDestroy(bg);
+      return Q2X_ERR_HIP;
+    }
+    plan->graph = bg;
+    plan->exec = bx;
+    plan->mode = plan->sched.mode;
     plan->graph_ws = workspace;
-    return Q2X_OK;  // the last replay left the result in place
+    plan->tuned = true;
+    std::lock_guard<std::mutex> g(tune_mu());
+    tune_cache()[key] = plan->sched;
+    if (cache_path) {
+      FILE* f = fopen(cache_path, "a");
+      if (f) {
+        fprintf(f, "%s\t%d %d %d\n", key.c_str(), plan->sched.mode, plan->sched.split, plan->sched.merge);
+        fclose(f);
+      }
+    }
+    return Q2X_OK;
   }
-  if (capture(plan, ws, mode, &plan->graph, &plan->exec) != hipSuccess) return Q2X_ERR_HIP;
-  plan->mode = mode;
+  if (!upload_table(plan)) return Q2X_ERR_HIP;
+  if (capture(plan, ws, plan->sched.mode, &plan->graph, &plan->exec) != hipSuccess) return Q2X_ERR_HIP;
+  plan->mode = plan->sched.mode;
   plan->graph_ws = workspace;
   return hipGraphLaunch(plan->exec, s) == hipSuccess ? Q2X_OK : Q2X_ERR_HIP;
 }
 
 q2x_status q2x_batch_launch(q2x_plan* plan, void* workspace, size_t workspace_bytes, void* stream) {
   if (!plan) return Q2X_ERR_ARG;
-  if (!workspace || ((uintptr_t)workspace % kAlign) != 0 || workspace_bytes < plan->total) return Q2X_ERR_WORKSPACE;
+  if (!workspace || ((uintptr_t)workspace % kAlign) != 0 || workspace_bytes < plan->ws_need) return Q2X_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   char* ws = (char*)workspace;
-  if (hipMemcpyAsync(ws + plan->off_table, plan->table.data(), plan->table.size(), hipMemcpyHostToDevice, s) !=
-      hipSuccess)
+  const Layout& L = plan->lay;
+  if (hipMemcpyAsync(ws + L.off_table, L.table.data(), L.table.size(), hipMemcpyHostToDevice, s) != hipSuccess)
     return Q2X_ERR_HIP;
-  return enqueue(plan, ws, ws + plan->off_table, 0, s) == hipSuccess ? Q2X_OK : Q2X_ERR_HIP;
+  return enqueue(plan, ws, ws + L.off_table, 0, s) == hipSuccess ? Q2X_OK : Q2X_ERR_HIP;
 }
 
 q2x_status q2x_batch_job_status(const q2x_plan* plan, const void* workspace, int job, void* stream,
                                 uint32_t* device_flags, int64_t* n_degenerate, int64_t* n_skipped) {
   if (!plan || !workspace || job < 0 || job >= plan->n_jobs) return Q2X_ERR_ARG;
-  return q2x_status_get((const char*)workspace + plan->off_status + (size_t)job * sizeof(Status), stream,
+  return q2x_status_get((const char*)workspace + plan->lay.off_status + (size_t)job * sizeof(Status), stream,
                         device_flags, n_degenerate, n_skipped);
 }
 
@@ -487,6 +746,22 @@ void q2x_batch_destroy(q2x_plan* plan) {
     if (c) (void)hipStreamDestroy(c);
   if (plan->dev_table) (void)hipFree(plan->dev_table);
   delete plan;
+}
+
+q2x_status q2x_tune_cache_load(const char* path) {
+  if (!path) return Q2X_ERR_ARG;
+  std::lock_guard<std::mutex> g(tune_mu());
+  return cache_load_locked(path) < 0 ? Q2X_ERR_ARG : Q2X_OK;
+}
+
+q2x_status q2x_tune_cache_save(const char* path) {
+  if (!path) return Q2X_ERR_ARG;
+  std::lock_guard<std::mutex> g(tune_mu());
+  FILE* f = fopen(path, "w");
+  if (!f) return Q2X_ERR_ARG;
+  for (const auto& kv : tune_cache())
+    fprintf(f, "%s\t%d %d %d\n", kv.first.c_str(), kv.second.mode, kv.second.split, kv.second.merge);
+  return fclose(f) == 0 ? Q2X_OK : Q2X_ERR_ARG;
 }
 
 }  // extern "C"

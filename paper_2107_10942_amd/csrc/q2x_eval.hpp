@@ -22,6 +22,61 @@
 
 namespace q2x {
 
+// Both parts of every order of one recursion array (one lane per element).
+template <typename T, int P1>
+struct CArr {
+  T r[P1];
+  T i[P1];
+};
+
+// One application of the ladder operator of Sec. 3.4, Eqs. (50)-(51) (tilde
+// form), degree N from degree N-1, both parts in one lane (the recursion
+// kernel's split form, ladder(), has the full statement):
+//   out^0 = 2 Re(eta F^1) - z F^0 + add^0
+//   out^m = -xi F^{m-1} + eta F^{m+1} - z F^m + add^m,   m >= 1,
+// xi = xr + i xi, eta = conj(xi), z; (xr2, xi2) = 2 (xr, xi).
+template <int N, bool ADD, typename T, int P1>
+__device__ __forceinline__ void ladder(CArr<T, P1>& out, const CArr<T, P1>& F, const CArr<T, P1>& add, T xr, T xi,
+                                       T z, T xr2, T xi2) {
+  static_assert(N >= 1 && N < P1, "degree out of range");
+  {
+    T v = ADD ? fmaT(-z, F.r[0], add.r[0]) : -z * F.r[0];
+    if constexpr (N - 1 >= 1) {
+      v = fmaT(xr2, F.r[1], v);
+      v = fmaT(xi2, F.i[1], v);
+    }
+    out.r[0] = v;
+    out.i[0] = T(0);
+  }
+  static_for<1, N + 1>([&](auto MM) Q2X_INLINE {
+    constexpr int m = decltype(MM)::value;
+    const T amr = F.r[m - 1];
+    // -xi F^{m-1}:  re -= xr Ar - xi Ai ;  im -= xr Ai + xi Ar
+    T re = ADD ? fmaT(-xr, amr, add.r[m]) : -xr * amr;
+    T im = ADD ? fmaT(-xi, amr, add.i[m]) : -xi * amr;
+    if constexpr (m - 1 > 0) {
+      const T ami = F.i[m - 1];
+      re = fmaT(xi, ami, re);
+      im = fmaT(-xr, ami, im);
+    }
+    // eta F^{m+1}:  re += xr Br + xi Bi ;  im += xr Bi - xi Br
+    if constexpr (m + 1 <= N - 1) {
+      const T apr = F.r[m + 1], api = F.i[m + 1];
+      re = fmaT(xr, apr, re);
+      re = fmaT(xi, api, re);
+      im = fmaT(xr, api, im);
+      im = fmaT(-xi, apr, im);
+    }
+    // -z F^m
+    if constexpr (m <= N - 1) {
+      re = fmaT(-z, F.r[m], re);
+      im = fmaT(-z, F.i[m], im);
+    }
+    out.r[m] = re;
+    out.i[m] = im;
+  });
+}
+
 template <int P, int KIND, typename T>
 __global__ __launch_bounds__(kTile) void q2x_eval_kernel(EvalArgs a, int64_t n_tiles) {
   using KI = KindInfo<KIND>;

@@ -8,8 +8,9 @@
 
 namespace q2x {
 
-constexpr int kTile = 64;            // elements per wavefront tile (one lane per element)
+constexpr int kTile = 64;            // lanes of a tile workgroup (one wavefront)
 constexpr int kWave = 64;            // CDNA wavefront width
+constexpr int kTileElems = 32;       // elements per recursion tile (two lanes per element)
 constexpr double kInv4Pi = 0.07957747154594766788;  // 1/(4 pi)
 constexpr double k4Pi = 12.566370614359172954;
 
@@ -63,7 +64,7 @@ struct TileArgs {
   int norm;
   int accumulate;
   int count_bad_ids;         // presorted input (no bucketing pass): count ids outside [0, n_boxes) here
-  int32_t te;                // elements per tile (1..64; tile t covers sorted positions [t te, (t + 1) te))
+  int32_t te;                // elements per tile (1..32; tile t covers sorted positions [t te, (t + 1) te))
   int64_t n_split;           // tiles that get two workgroups (0 <= n_split <= n_tiles <= 2048 when > 0; spread evenly:
                              // tile t is split iff floor((t+1) n_split / n_tiles) > floor(t n_split / n_tiles));
                              // workgroup w of a split tile stages and reduces the chunks J with J % 2 == w.
@@ -94,12 +95,9 @@ struct BatchJob {
   int32_t te;          // elements per tile: the single call's (tile_width), so the sums are bitwise the same
 };
 
-// Elements per tile of a call: 64 (one per lane).  Narrower tiles that
-// spread a launch evenly over the wave slots (two FP32 / one FP64 wave per
-// SIMD) were measured on the 81,920-triangle sphere and gave nothing: the
-// launch time is set by the tiles with the most box segments (a flush per
-// segment and chunk), not by the number of tiles per SIMD.
-inline int tile_width(int64_t, int) { return kTile; }
+// Elements per tile of a call: 32, two lanes per element (the recursion
+// kernel's layout).
+inline int tile_width(int64_t, int) { return kTileElems; }
 
 // Arguments of the receiving-side kernel (integrals of local expansions over
 // elements; one lane per element, no reduction).

@@ -1,9 +1,15 @@
 // q2x_tile.hpp -- the Q2X recursion + box reduction kernel (one wavefront per
-// tile of up to 64 box-sorted elements, one lane per element).
+// tile of up to 32 box-sorted elements, two adjacent lanes per element).
 //
-// Per lane: FP64 geometry of its element relative to its box centre, then the
-// m >= 0 ("tilde") recursions of Sec. 3.4, Eqs. (50)-(56), degree by degree,
-// with the whole recursion state in VGPRs (template order P, fully unrolled).
+// Per element: FP64 geometry relative to its box centre, then the m >= 0
+// ("tilde") recursions of Sec. 3.4, Eqs. (50)-(56), degree by degree, with
+// the whole recursion state in VGPRs (template order P, fully unrolled).
+// Lane 2e holds the real parts of element e's orders, lane 2e + 1 the
+// imaginary parts.  Each lane forms its own part of every new order from its
+// own parts of the previous degree and its neighbour's (one DPP lane swap per
+// order, read into a fresh register): six instructions per order instead of
+// ten in one lane, so a wave's instruction stream is about 40% shorter than
+// with one lane per element, for half as many elements.
 // The recursion carries G_n = (n+k)! t~_n (k = nesting depth), which removes
 // every division from Eqs. (50)-(55) and keeps the values O(1) at any order.
 // The FP32 path runs it on Y = (x - c)/a_e, a_e the element's largest vertex
@@ -11,16 +17,18 @@
 // position (degree n of the result scales as a_e^n); the FP64 path runs on
 // x - c unscaled.
 // An element kind has one output (single layer, double layer, segment, tet)
-// or two (single and double layer of one triangle mesh from one recursion).
+// or two (single and double layer of one triangle mesh from one recursion) or
+// three (segments with a vector density).
 // Every degree's outputs go to an LDS stage (real and imaginary parts in
-// separate rows), and the FP64 factors s_e a_e^n / (n+k)!
-// (s_e = sigma_e J_e / 4pi) to a small table beside it.  When a group of
-// outputs ("chunk", <= CMAX coefficients) is complete the wavefront transposes
-// through LDS -- lane = coefficient -- and walks the 64 elements in order, one
-// box segment at a time, summing factor * value in FP64.  Boxes wholly inside
-// the tile are finalised and stored directly; a box cut by a tile edge leaves
-// a raw partial sum for the fix-up kernel.  The order of every sum is fixed by
-// the element order, so results are bitwise reproducible.
+// separate rows, each written by the lane that holds it), and the FP64
+// factors s_e a_e^n / (n+k)! (s_e = sigma_e J_e / 4pi) to a small table
+// beside it.  When a group of outputs ("chunk", <= CMAX coefficients) is
+// complete the wavefront transposes through LDS -- lane = coefficient -- and
+// walks the tile's elements in order, one box segment at a time, summing
+// factor * value in FP64.  Boxes wholly inside the tile are finalised and
+// stored directly; a box cut by a tile edge leaves a raw partial sum for the
+// fix-up kernel.  The order of every sum is fixed by the element order, so
+// results are bitwise reproducible.
 #pragma once
 
 #include "q2x_internal.hpp"
@@ -44,12 +52,6 @@ __device__ __forceinline__ void static_for(F&& f) {
   }
 }
 
-template <typename T, int P1>
-struct CArr {
-  T r[P1];
-  T i[P1];
-};
-
 // Cross product with every product rounded on its own (no FMA contraction),
 // so that u x u is exactly zero and a repeated vertex gives J = 0.
 __device__ __forceinline__ void cross_nofma(double ux, double uy, double uz, double vx, double vy, double vz,
@@ -63,56 +65,90 @@ __device__ __forceinline__ void cross_nofma(double ux, double uy, double uz, dou
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-// One application of the ladder operator of Sec. 3.4, Eqs. (50)-(51) (tilde
-// form), producing degree N (orders 0..N) from degree N-1 (orders 0..N-1):
+// One part (real or imaginary) of every order of one recursion array.
+template <typename T, int P1>
+struct CVec {
+  T v[P1];
+};
+
+// Per-lane coefficients of one application of the ladder operator of Sec.
+// 3.4, Eqs. (50)-(51) (tilde form), which makes degree N (orders 0..N) from
+// degree N-1 (orders 0..N-1):
 //   out^0 = 2 Re(eta F^1) - z F^0 + add^0
 //   out^m = -xi F^{m-1} + eta F^{m+1} - z F^m + add^m,   m >= 1,
-// with xi = (Y_x + i Y_y)/2 = xr + i xi, eta = conj(xi), z = Y_z and F^k = 0
+// with xi = x + i y (the vertex or normal, halved), eta = conj(xi) and F^k = 0
 // for k > N-1.  The recursions of Eqs. (50)-(55) divide this by (n+k) at the
 // k-th nesting level; the kernel carries G_n = (n+k)! F_n instead, for which
-// the division disappears (G_n = D G_{n-1} + G^{(k-1)}_n, every start value 1),
-// and folds 1/(n+k)! into the FP64 per-degree factor.  Every real output is a
-// chain of FMAs (5 for an interior order with a source term).
-// (xr2, xi2) = 2 (xr, xi).
+// the division disappears (G_n = D G_{n-1} + G^{(k-1)}_n, every start value
+// 1), and folds 1/(n+k)! into the FP64 per-degree factor.
+// Split into parts, with f the lane's own part and g its neighbour's (the
+// real lane's g is the imaginary part and the other way round):
+//   out^m = -x (f^{m-1} - f^{m+1}) + s y (g^{m-1} + g^{m+1}) - z f^m + add^m
+// with s = +1 on the real lane and -1 on the imaginary lane, and
+//   out^0 = 2x f^1 + 2y g^1 - z f^0 + add^0   (real lane),
+//   out^0 = -z f^0 + add^0 = 0               (imaginary lane: f^0 = 0).
+template <typename T>
+struct LCoef {
+  T x, ys, mz, c0f, c0g;  // x, s y, -z, and the order-0 factors of f^1, g^1
+};
+
+template <typename T>
+__device__ __forceinline__ LCoef<T> ladder_coef(bool imag, T x, T y, T z, T x2, T y2) {
+  LCoef<T> c;
+  c.x = x;
+  c.ys = imag ? -y : y;
+  c.mz = -z;
+  c.c0f = imag ? T(0) : x2;
+  c.c0g = imag ? T(0) : y2;
+  return c;
+}
+
+// The neighbouring lane's value (lanes 2e and 2e + 1 exchange: DPP
+// quad_perm [1,0,3,2]).
+__device__ __forceinline__ float neighbour(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double neighbour(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0xB1, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// The neighbour's parts of orders 0..N-1 of an array.
+template <int N, typename T, int P1>
+__device__ __forceinline__ void spread(const CVec<T, P1>& F, T (&G)[P1]) {
+  static_for<0, N>([&](auto MM) Q2X_INLINE {
+    constexpr int m = decltype(MM)::value;
+    G[m] = neighbour(F.v[m]);
+  });
+}
+
+// The lane's part of degree N from degree N-1: F (own parts), G (the
+// neighbour's parts of orders 0..N-1, from spread), add (own parts of the
+// source term).  Every output is a chain of FMAs (5 for an interior order
+// with a source).
 template <int N, bool ADD, typename T, int P1>
-__device__ __forceinline__ void ladder(CArr<T, P1>& out, const CArr<T, P1>& F, const CArr<T, P1>& add, T xr, T xi,
-                                       T z, T xr2, T xi2) {
+__device__ __forceinline__ void ladder(CVec<T, P1>& out, const CVec<T, P1>& F, const T (&G)[P1],
+                                       const CVec<T, P1>& add, const LCoef<T>& c) {
   static_assert(N >= 1 && N < P1, "degree out of range");
   {
-    T v = ADD ? fmaT(-z, F.r[0], add.r[0]) : -z * F.r[0];
+    T v = ADD ? fmaT(c.mz, F.v[0], add.v[0]) : c.mz * F.v[0];
     if constexpr (N - 1 >= 1) {
-      v = fmaT(xr2, F.r[1], v);
-      v = fmaT(xi2, F.i[1], v);
+      v = fmaT(c.c0g, G[1], v);
+      v = fmaT(c.c0f, F.v[1], v);
     }
-    out.r[0] = v;
-    out.i[0] = T(0);
+    out.v[0] = v;
   }
   static_for<1, N + 1>([&](auto MM) Q2X_INLINE {
     constexpr int m = decltype(MM)::value;
-    const T amr = F.r[m - 1];
-    // -xi F^{m-1}:  re -= xr Ar - xi Ai ;  im -= xr Ai + xi Ar
-    T re = ADD ? fmaT(-xr, amr, add.r[m]) : -xr * amr;
-    T im = ADD ? fmaT(-xi, amr, add.i[m]) : -xi * amr;
-    if constexpr (m - 1 > 0) {
-      const T ami = F.i[m - 1];
-      re = fmaT(xi, ami, re);
-      im = fmaT(-xr, ami, im);
-    }
-    // eta F^{m+1}:  re += xr Br + xi Bi ;  im += xr Bi - xi Br
+    T v = ADD ? fmaT(c.ys, G[m - 1], add.v[m]) : c.ys * G[m - 1];
     if constexpr (m + 1 <= N - 1) {
-      const T apr = F.r[m + 1], api = F.i[m + 1];
-      re = fmaT(xr, apr, re);
-      re = fmaT(xi, api, re);
-      im = fmaT(xr, api, im);
-      im = fmaT(-xi, apr, im);
+      v = fmaT(c.ys, G[m + 1], v);
+      v = fmaT(c.x, F.v[m + 1], v);
     }
-    // -z F^m
-    if constexpr (m <= N - 1) {
-      re = fmaT(-z, F.r[m], re);
-      im = fmaT(-z, F.i[m], im);
-    }
-    out.r[m] = re;
-    out.i[m] = im;
+    if constexpr (m <= N - 1) v = fmaT(c.mz, F.v[m], v);
+    v = fmaT(-c.x, F.v[m - 1], v);
+    out.v[m] = v;
   });
 }
 
@@ -350,6 +386,17 @@ __device__ __forceinline__ ElemGeom<NV, T> element_geometry(const double* verts,
   return g;
 }
 
+// Bit e of the result = bit 2e of x (element e's lead lane in a ballot).
+__device__ __forceinline__ uint64_t even_bits(uint64_t x) {
+  x &= 0x5555555555555555ull;
+  x = (x | (x >> 1)) & 0x3333333333333333ull;
+  x = (x | (x >> 2)) & 0x0F0F0F0F0F0F0F0Full;
+  x = (x | (x >> 4)) & 0x00FF00FF00FF00FFull;
+  x = (x | (x >> 8)) & 0x0000FFFF0000FFFFull;
+  x = (x | (x >> 16)) & 0x00000000FFFFFFFFull;
+  return x;
+}
+
 __device__ __forceinline__ int64_t readlane64(int64_t v, int i) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, i);
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), i);
@@ -368,7 +415,9 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
   // padded row stride (elements) of the stage: SSTR sizeof(T) = 16 (mod 128),
   // so rows start 16-byte aligned and the 16-byte reads of eight lanes (eight
   // rows) cover the 32 banks once
-  constexpr int SSTR = (sizeof(T) == 4) ? kTile + 4 : kTile + 2;
+  constexpr int TE = kTileElems;  // elements per tile (lanes e and e + TE)
+  static_assert(2 * TE == kTile, "two lanes per element");
+  constexpr int SSTR = (sizeof(T) == 4) ? TE + 4 : TE + 2;
   constexpr int NCT = tri(P + 1);
   constexpr bool SCALED = PrecInfo<T>::scaled;
   using Plan = ChunkPlan<P, CMAX, NOUT>;
@@ -378,7 +427,7 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
   __shared__ __align__(16) T stage[2 * CMAX * SSTR];
   // FP32 path: scale exponents of every box segment of the tile (row 0: the
   // element scales a_e, row 1 + o: the weights s_e of output o)
-  __shared__ int sexp[SCALED ? (NOUT + 1) * kTile : 1];
+  __shared__ int sexp[SCALED ? (NOUT + 1) * TE : 1];
 
   // a split tile has two workgroups (consecutive virtual ids, so the same
   // XCD): both run the recursion, workgroup wpart stages and reduces the chunks
@@ -400,8 +449,11 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
     ns = ((t + 1) * s2 / n > t * s2 / n) ? 2 : 1;
   }
   const int lane = threadIdx.x;
+  const int el = lane >> 1;        // the lane's element in the tile
+  const bool imag = lane & 1;      // the lane holds imaginary parts
+  const bool lead = !imag;         // the lane that counts and records the element
   TileArgs a = args;
-  int te = a.te;               // elements per tile (uniform, 1..64; a batch job's own)
+  int te = a.te;               // elements per tile (uniform, 1..TE; a batch job's own)
   int64_t q0 = tile * te;      // first sorted position of the tile
   int64_t pos_end = a.n_pos;   // end of the sorted range the tile belongs to
   int64_t key_off = 0;         // sorted keys are key_off + box id
@@ -442,8 +494,8 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
   }
   if (q0 >= pos_end) return;  // uniform (past the job's valid elements)
   const int ne = (int)min<int64_t>(te, pos_end - q0);
-  const int64_t q = q0 + lane;
-  const bool in_range = lane < ne;
+  const int64_t q = q0 + el;
+  const bool in_range = el < ne;
 
   // ---- element, box and FP64 geometry (Sec. 3.1, Eqs. (8)-(9); Sec. 3.3, Eq. (21))
   const int key = in_range ? (int)(a.keys[q] - key_off) : INT32_MIN;
@@ -460,11 +512,10 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
   uint32_t flag = gm.flag;
   const double J = gm.J, nx = gm.nx, ny = gm.ny, nz = gm.nz, scl = gm.scl;
   const bool degenerate = ok && !(J > 0.0);
-  const T* vxr = gm.vxr;
-  const T* vxi = gm.vxi;
-  const T* vz = gm.vz;
-  const T* vxr2 = gm.vxr2;
-  const T* vxi2 = gm.vxi2;
+  // the lane's ladder coefficients about every vertex
+  LCoef<T> cv[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) cv[k] = ladder_coef(imag, gm.vxr[k], gm.vxi[k], gm.vz[k], gm.vxr2[k], gm.vxi2[k]);
   // s_e = sigma_e J / (4 pi) (Sec. 3.2, Eq. (20)); 0 for skipped elements
   double sw[NOUT];
   static_for<0, NOUT>([&](auto OO) Q2X_INLINE {
@@ -476,7 +527,7 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
   // outside [0, B) counting as -1 / B (the fix-up kernel reads it)
   const int key_prev = (in_range && q > 0) ? (int)(a.keys[q - 1] - key_off) : INT32_MIN;
   const int ncoef_out = (a.p + 1) * (a.p + 1);
-  if (in_range && !batch && wpart == 0) {
+  if (in_range && lead && !batch && wpart == 0) {
     const int64_t nb = a.n_boxes;
     const int64_t kc = key < 0 ? -1 : (key >= nb ? nb : key);
     const int64_t kp = (q == 0 || key_prev < 0) ? -1 : (key_prev >= nb ? nb : key_prev);
@@ -488,8 +539,8 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
 
   // ---- status (one atomic per wavefront and counter)
   {
-    const uint64_t deg_mask = __ballot(degenerate);
-    const uint64_t skip_mask = __ballot((box_ok && !ok) || (a.count_bad_ids && in_range && !box_ok));
+    const uint64_t deg_mask = __ballot(lead && degenerate);
+    const uint64_t skip_mask = __ballot(lead && ((box_ok && !ok) || (a.count_bad_ids && in_range && !box_ok)));
     uint32_t fall = 0;
 #pragma unroll
     for (int b = 0; b < 5; ++b)
@@ -503,9 +554,10 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
   }
 
   // ---- box boundaries inside the tile (uniform bit mask), open tile edges
-  const bool seg_start = in_range && (lane == 0 || key != key_prev);
-  const uint64_t bnd = __ballot(seg_start);
-  const uint64_t vseg = __ballot(seg_start && box_ok);  // segments whose box is valid (flushed)
+  // (bit i: element i, from its lead lane 2i)
+  const bool seg_start = lead && in_range && (el == 0 || key != key_prev);
+  const uint64_t bnd = even_bits(__ballot(seg_start));
+  const uint64_t vseg = even_bits(__ballot(seg_start && box_ok));  // segments whose box is valid (flushed)
   bool head_open = false, tail_open = false;
   if (q0 > 0) head_open = (a.keys[q0 - 1] == a.keys[q0]);
   if (ne == te && q0 + te < pos_end) tail_open = (a.keys[q0 + te] == a.keys[q0 + te - 1]);
@@ -530,11 +582,13 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
 #pragma unroll
   for (int o = 0; o < NOUT; ++o) seg_es[o] = 0;
   if constexpr (SCALED) {
-    const int si = __popcll(bnd & ((2ull << lane) - 1)) - 1;  // box segment of this element
+    const int si = __popcll(bnd & ((2ull << el) - 1)) - 1;  // box segment of this element
+    if (lead) {
 #pragma unroll
-    for (int t = 0; t <= NOUT; ++t) sexp[t * kTile + lane] = kNoExp;
+      for (int t = 0; t <= NOUT; ++t) sexp[t * TE + el] = kNoExp;
+    }
     __syncthreads();
-    if (ok) {
+    if (ok && lead) {
       int ea;
       (void)frexp(scl, &ea);
       atomicMax(&sexp[si], ea);
@@ -543,14 +597,14 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
         if (sw[o] != 0.0) {
           int es;
           (void)frexp(sw[o], &es);
-          atomicMax(&sexp[(1 + o) * kTile + si], es);
+          atomicMax(&sexp[(1 + o) * TE + si], es);
         }
       }
     }
     __syncthreads();
     seg_eb = sexp[si];
 #pragma unroll
-    for (int o = 0; o < NOUT; ++o) seg_es[o] = sexp[(1 + o) * kTile + si];
+    for (int o = 0; o < NOUT; ++o) seg_es[o] = sexp[(1 + o) * TE + si];
 #pragma unroll
     for (int o = 0; o < NOUT; ++o) wgt[o] = 0.0;
     if (ok) {
@@ -662,11 +716,11 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
     };
     auto next_segment = [&](int i) Q2X_INLINE {
       seg = i;
-      boff = readlane64(row_off, i);
+      boff = readlane64(row_off, 2 * i);
       if constexpr (SCALED) {
-        eb = __builtin_amdgcn_readlane(seg_eb, i);
+        eb = __builtin_amdgcn_readlane(seg_eb, 2 * i);
 #pragma unroll
-        for (int q = 0; q < NOUT; ++q) es[q] = __builtin_amdgcn_readlane(seg_es[q], i);
+        for (int q = 0; q < NOUT; ++q) es[q] = __builtin_amdgcn_readlane(seg_es[q], 2 * i);
       }
     };
     const T* pv = stage + ((h ? CMAX : 0) + (act ? c : 0)) * SSTR;
@@ -728,6 +782,7 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
   // chunk J, decoded at compile time (natural chunk ends inside the recursion)
   auto reduce_chunk = [&](auto JJc) Q2X_INLINE {
     constexpr int J = decltype(JJc)::value;
+    if (J % ns != wpart) return;  // uniform: the other workgroup's chunk
     constexpr int K0 = J * CMAX;
     constexpr int CJ = (Plan::K - K0 < CMAX) ? Plan::K - K0 : CMAX;
     constexpr int UF = Plan::first_unit(J), UL = Plan::last_unit(J);
@@ -762,7 +817,9 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
 
   // output o of degree N: stage it, weighted, and reduce each chunk as soon
   // as it is full
-  auto emit = [&](auto NNc, auto OO, const CArr<T, P1>& V) Q2X_INLINE {
+  // (a split tile's workgroups both stage every chunk and reduce their own)
+  T* const slane = stage + (imag ? CMAX * SSTR : 0) + el;
+  auto emit = [&](auto NNc, auto OO, const CVec<T, P1>& V) Q2X_INLINE {
     constexpr int N = decltype(NNc)::value;
     constexpr int o = decltype(OO)::value;
     constexpr int u = NOUT * N + KI::slot(o);
@@ -773,9 +830,7 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
       constexpr int m = decltype(MM)::value;
       constexpr int kk = k0 + m;
       constexpr int row = kk % CMAX;
-      if ((kk / CMAX) % ns != wpart) return;  // uniform: another workgroup's chunk
-      stage[row * SSTR + lane] = V.r[m] * w;
-      stage[(CMAX + row) * SSTR + lane] = V.i[m] * w;
+      slane[row * SSTR] = V.v[m] * w;
       if constexpr (row == CMAX - 1) reduce_chunk(IC<kk / CMAX>{});  // chunk kk / CMAX is full
     });
     if constexpr (SCALED) {
@@ -784,43 +839,50 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
       constexpr double inv_next = 1.0 / (double)(N + 1 + KI::depth(o));
       wgt[o] *= inv_next;
     }
-    if constexpr (k1 % CMAX != 0 && k1 == Plan::K) {  // last, partly filled chunk
-      if (j1 % ns == wpart) reduce_chunk(IC<j1>{});
-    }
+    if constexpr (k1 % CMAX != 0 && k1 == Plan::K) reduce_chunk(IC<j1>{});  // last, partly filled chunk
   };
 
-  // one degree of every array of the chain: nS (degree N) from S (degree N-1)
-  auto advance = [&](auto NNc, CArr<T, P1>(&nS)[NCH], const CArr<T, P1>(&S)[NCH]) Q2X_INLINE {
+  // one degree of every array of the chain: nS (degree N) from S (degree N-1).
+  // LASTG: the neighbour's parts of the last array, already spread (USE_LAST).
+  auto advance = [&](auto NNc, auto USE_LAST, CVec<T, P1>(&nS)[NCH], const CVec<T, P1>(&S)[NCH],
+                     const T(&LASTG)[P1]) Q2X_INLINE {
     constexpr int N = decltype(NNc)::value;
     static_for<0, NCH>([&](auto KK) Q2X_INLINE {
       constexpr int k = decltype(KK)::value;
       constexpr int v = KI::vert(k);
-      if constexpr (k == 0)
-        ladder<N, false>(nS[0], S[0], S[0], vxr[v], vxi[v], vz[v], vxr2[v], vxi2[v]);
-      else
-        ladder<N, true>(nS[k], S[k], nS[k - 1], vxr[v], vxi[v], vz[v], vxr2[v], vxi2[v]);
+      auto step = [&](const T(&G)[P1]) Q2X_INLINE {
+        if constexpr (k == 0)
+          ladder<N, false>(nS[0], S[0], G, S[0], cv[v]);
+        else
+          ladder<N, true>(nS[k], S[k], G, nS[k - 1], cv[v]);
+      };
+      if constexpr (decltype(USE_LAST)::value && k == NCH - 1) {
+        step(LASTG);
+      } else {
+        T G[P1];
+        spread<N>(S[k], G);
+        step(G);
+      }
     });
   };
 
   // ---- recursion over degrees (Sec. 3.4).  Nested rather than sequential, so
   // that skipping the degrees above p merges no register state.
-  CArr<T, P1> S0[NCH];
+  CVec<T, P1> S0[NCH];
 #pragma unroll
-  for (int k = 0; k < NCH; ++k) {
-    S0[k].r[0] = T(1);
-    S0[k].i[0] = T(0);
-  }
+  for (int k = 0; k < NCH; ++k) S0[k].v[0] = imag ? T(0) : T(1);
   constexpr bool HAS_DBL = KI::dbl(NOUT - 1);
   if constexpr (!HAS_DBL) {
     // S holds degree N; emit the chain's last array for every output (one
     // weight per output)
-    auto rec = [&](auto self, auto NNc, const CArr<T, P1>(&S)[NCH]) Q2X_INLINE -> void {
+    auto rec = [&](auto self, auto NNc, const CVec<T, P1>(&S)[NCH]) Q2X_INLINE -> void {
       constexpr int N = decltype(NNc)::value;
       static_for<0, NOUT>([&](auto OO) Q2X_INLINE { emit(IC<N>{}, OO, S[NCH - 1]); });
       if constexpr (N < P) {
         if (N < p) {
-          CArr<T, P1> nS[NCH];
-          advance(IC<N + 1>{}, nS, S);
+          CVec<T, P1> nS[NCH];
+          T none[P1];
+          advance(IC<N + 1>{}, IC<0>{}, nS, S, none);
           self(self, IC<N + 1>{}, nS);
         }
       }
@@ -831,33 +893,34 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
     // (Sec. 3.4, Eq. (56)); with two outputs the single layer (output 0) is i~_N.
     // S holds degree max(N-1, 0).
     constexpr int OD = NOUT - 1;
-    const T hnx = (T)(0.5 * nx), hny = (T)(0.5 * ny), tnz = (T)nz, nx2 = (T)nx, ny2 = (T)ny;
-    auto rec = [&](auto self, auto NNc, const CArr<T, P1>(&S)[NCH]) Q2X_INLINE -> void {
+    const LCoef<T> cn = ladder_coef(imag, (T)(0.5 * nx), (T)(0.5 * ny), (T)nz, (T)nx, (T)ny);
+    auto rec = [&](auto self, auto NNc, const CVec<T, P1>(&S)[NCH]) Q2X_INLINE -> void {
       constexpr int N = decltype(NNc)::value;
       if constexpr (N == 0) {
-        CArr<T, P1> Z;
-        Z.r[0] = T(0);
-        Z.i[0] = T(0);
+        CVec<T, P1> Z;
+        Z.v[0] = T(0);
         emit(IC<0>{}, IC<OD>{}, Z);
         if constexpr (NOUT == 2) emit(IC<0>{}, IC<0>{}, S[NCH - 1]);
         if (0 < p) self(self, IC<1>{}, S);
       } else {
+        T G[P1];  // the neighbour's parts of the last array (degree N-1)
+        spread<N>(S[NCH - 1], G);
         {
-          CArr<T, P1> L;
-          ladder<N, false>(L, S[NCH - 1], S[NCH - 1], hnx, hny, tnz, nx2, ny2);
+          CVec<T, P1> L;
+          ladder<N, false>(L, S[NCH - 1], G, S[NCH - 1], cn);
           emit(IC<N>{}, IC<OD>{}, L);
         }
         if constexpr (NOUT == 2) {
-          CArr<T, P1> nS[NCH];
-          advance(IC<N>{}, nS, S);
+          CVec<T, P1> nS[NCH];
+          advance(IC<N>{}, IC<1>{}, nS, S, G);
           emit(IC<N>{}, IC<0>{}, nS[NCH - 1]);
           if constexpr (N < P) {
             if (N < p) self(self, IC<N + 1>{}, nS);
           }
         } else if constexpr (N < P) {
           if (N < p) {
-            CArr<T, P1> nS[NCH];
-            advance(IC<N>{}, nS, S);
+            CVec<T, P1> nS[NCH];
+            advance(IC<N>{}, IC<1>{}, nS, S, G);
             self(self, IC<N + 1>{}, nS);
           }
         }

@@ -29,11 +29,19 @@ EXPORTS = ("q2x_workspace_bytes", "q2x_bucket_workspace_bytes", "q2x_bucket", "q
            "q2x_profile_read", "q2x_version", "q2x_batch_plan", "q2x_batch_workspace_bytes", "q2x_batch_run", "q2x_batch_launch",
            "q2x_batch_job_status", "q2x_batch_groups", "q2x_batch_mode", "q2x_batch_destroy",
            "q2x_eval_workspace_bytes", "q2x_eval", "q2x_m2m_workspace_bytes", "q2x_m2m",
-           "q2x_near_workspace_bytes", "q2x_near", "q2x_peak_measure")
+           "q2x_near_workspace_bytes", "q2x_near", "q2x_peak_measure", "q2x_batch_get_schedule",
+           "q2x_batch_set_schedule", "q2x_tune_cache_load", "q2x_tune_cache_save", "q2x_build_id")
+MERGE_ALL = 2 ** 31 - 1  # q2x_schedule.merge: one group per kind and precision
 
 
 class Q2XError(RuntimeError):
     pass
+
+
+class Schedule(ctypes.Structure):
+    """Mirror of `q2x_schedule` (include/q2x.h)."""
+    _fields_ = [("mode", ctypes.c_int32), ("split", ctypes.c_int32), ("merge", ctypes.c_int32),
+                ("tuned", ctypes.c_int32)]
 
 
 class Job(ctypes.Structure):
@@ -103,6 +111,16 @@ def lib():
         L.q2x_batch_mode.restype = ci
         L.q2x_batch_destroy.argtypes = [vp]
         L.q2x_batch_destroy.restype = None
+        L.q2x_batch_get_schedule.argtypes = [vp, ctypes.POINTER(Schedule)]
+        L.q2x_batch_get_schedule.restype = ci
+        L.q2x_batch_set_schedule.argtypes = [vp, ctypes.POINTER(Schedule)]
+        L.q2x_batch_set_schedule.restype = ci
+        L.q2x_tune_cache_load.argtypes = [ctypes.c_char_p]
+        L.q2x_tune_cache_load.restype = ci
+        L.q2x_tune_cache_save.argtypes = [ctypes.c_char_p]
+        L.q2x_tune_cache_save.restype = ci
+        L.q2x_build_id.argtypes = []
+        L.q2x_build_id.restype = ctypes.c_char_p
         L.q2x_eval_workspace_bytes.argtypes = [i64, i64]
         L.q2x_eval_workspace_bytes.restype = sz
         L.q2x_eval.argtypes = [ci, vp, i64, vp, i64, vp, vp, i64, vp, ci, ci, cu, vp, vp, sz, vp]
@@ -355,6 +373,18 @@ class BatchPlan:
     def mode(self):
         return int(lib().q2x_batch_mode(self._h))
 
+    @property
+    def schedule(self):
+        """The plan's schedule: dict(mode, split, merge, tuned) (q2x_batch_get_schedule)."""
+        sc = Schedule()
+        _check(lib().q2x_batch_get_schedule(self._h, ctypes.byref(sc)))
+        return {"mode": sc.mode, "split": sc.split, "merge": sc.merge, "tuned": sc.tuned}
+
+    def set_schedule(self, mode=0, split=0, merge=0):
+        """Force a schedule (q2x_batch_set_schedule); the plan is then never tuned."""
+        sc = Schedule(int(mode), int(split), int(merge), 0)
+        _check(lib().q2x_batch_set_schedule(self._h, ctypes.byref(sc)))
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().q2x_batch_destroy(self._h)
@@ -577,3 +607,18 @@ def job_tensors(job, device="cuda"):
     t = lambda a, dt: torch.as_tensor(a, dtype=dt).contiguous().to(device)  # noqa: E731
     return (t(job.verts, torch.float64), t(job.elems, torch.int32), t(job.density, torch.float64),
             t(job.elem_box, torch.int32), t(job.box_center, torch.float64), t(job.box_radius, torch.float64))
+
+
+def tune_cache_load(path):
+    """Read batch schedules from a text file (q2x_tune_cache_load)."""
+    _check(lib().q2x_tune_cache_load(os.fsencode(path)))
+
+
+def tune_cache_save(path):
+    """Write every cached batch schedule to a text file (q2x_tune_cache_save)."""
+    _check(lib().q2x_tune_cache_save(os.fsencode(path)))
+
+
+def build_id():
+    """Hash of the library's sources (q2x_build_id)."""
+    return lib().q2x_build_id().decode()

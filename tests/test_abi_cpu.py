@@ -163,3 +163,29 @@ def test_near_and_m2m_argument_errors():
     assert m2m(wb=16) == -3 and m2m(w=None) == -3
     # parents written over the children being read
     assert m2m(child=vp(4096), out=vp(4096 + 16 * 81)) == -1
+
+
+def test_build_id_and_tune_cache_files(tmp_path):
+    """q2x_build_id is the hash of the library's sources; the tuning cache
+    reads and writes its text format (host-only calls), keeps well-formed
+    entries of any device or build, skips malformed lines and refuses a path
+    it cannot open."""
+    _ensure_built()
+    from paper_2107_10942_amd import build, q2x
+    assert q2x.build_id() == build.library_hash()
+    src = tmp_path / "in.txt"
+    src.write_text("gfx950:sramecc+:xnack-/256|0123456789abcdef|0,1,16,40;2560/6617\t1 0 1024\n"
+                   "not a cache line\n"
+                   "other|feedfacefeedface|4,0,20,7;448/30\t0 1 0\n"
+                   "bad|x|y\t7 0 0\n")
+    q2x.tune_cache_load(src)
+    out = tmp_path / "out.txt"
+    q2x.tune_cache_save(out)
+    lines = out.read_text().splitlines()
+    assert "gfx950:sramecc+:xnack-/256|0123456789abcdef|0,1,16,40;2560/6617\t1 0 1024" in lines
+    assert "other|feedfacefeedface|4,0,20,7;448/30\t0 1 0" in lines
+    assert not any(ln.startswith("bad|") or ln.startswith("not a") for ln in lines)
+    with pytest.raises(q2x.Q2XError):
+        q2x.tune_cache_load(tmp_path / "missing.txt")
+    with pytest.raises(q2x.Q2XError):
+        q2x.tune_cache_save(tmp_path / "no_such_dir" / "x.txt")

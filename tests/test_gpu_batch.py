@@ -199,3 +199,64 @@ def test_batch_jobs_against_the_oracle():
             assert err <= TOL[spec["precision"]], (j, kind, err)
         assert plan.status(j)[0] == 0
     plan.close()
+
+
+@pytest.mark.parametrize("sched", [(0, 0, 0), (1, 0, 0), (0, 1, 0), (1, 1, 1024), (0, 0, 2 ** 31 - 1),
+                                   (1, 1, 2 ** 31 - 1)])
+def test_every_schedule_equals_single_calls(sched):
+    """A forced schedule (capture mode, split tiles, merged order buckets)
+    changes no bit of any job's coefficients or status."""
+    import torch
+    from paper_2107_10942_amd import q2x
+    specs = _mixed_specs()
+    plan = q2x.BatchPlan(specs)
+    g0 = plan.groups
+    plan.set_schedule(*sched)
+    sc = plan.schedule
+    assert (sc["mode"], sc["split"], sc["merge"], sc["tuned"]) == (*sched, 2)
+    if sched[2] == q2x.MERGE_ALL:
+        # one group per (kind, precision) present
+        assert plan.groups == len({(s["kind"], s["precision"]) for s in specs}) < g0
+    outs = plan.run()
+    torch.cuda.synchronize()
+    assert plan.mode == sched[0]
+    _compare(plan, specs, outs)
+    plan.close()
+
+
+def test_tuning_is_cached_and_persisted(tmp_path):
+    """The first run times the candidate schedules and caches the winner
+    (keyed by device, library build and plan shape); a second plan of the
+    same shape takes it from the cache; a saved cache file reloads, and an
+    entry edited in the file is the schedule a new plan then uses."""
+    import torch
+    from paper_2107_10942_amd import q2x
+    specs = _mixed_specs()
+    plan = q2x.BatchPlan(specs)
+    outs = plan.run()
+    torch.cuda.synchronize()
+    sc = plan.schedule
+    assert sc["tuned"] == 1, sc
+    _compare(plan, specs, outs)
+    path = tmp_path / "tune.txt"
+    q2x.tune_cache_save(path)
+    lines = path.read_text().splitlines()
+    mine = [ln for ln in lines if ("|" + q2x.build_id() + "|") in ln]
+    assert mine, lines
+    plan2 = q2x.BatchPlan(specs)
+    plan2.run()
+    torch.cuda.synchronize()
+    assert plan2.schedule == sc
+    # edit the entries of this build to another schedule and reload
+    want = (1 - sc["mode"], 1 - sc["split"], 0 if sc["merge"] else q2x.MERGE_ALL)
+    edited = [ln.split("\t")[0] + "\t%d %d %d" % want if ("|" + q2x.build_id() + "|") in ln else ln for ln in lines]
+    path.write_text("\n".join(edited) + "\n")
+    q2x.tune_cache_load(path)
+    plan3 = q2x.BatchPlan(specs)
+    outs3 = plan3.run()
+    torch.cuda.synchronize()
+    s3 = plan3.schedule
+    assert (s3["mode"], s3["split"], s3["merge"], s3["tuned"]) == (*want, 1), s3
+    _compare(plan3, specs, outs3)
+    for p in (plan, plan2, plan3):
+        p.close()
