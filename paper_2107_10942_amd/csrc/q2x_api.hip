@@ -21,7 +21,12 @@ __global__ __launch_bounds__(256) void q2x_fixup_kernel(FixupArgs f) {
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   for (int64_t b = wave; b < f.n_boxes; b += nwaves) {
-    const int64_t s = f.n_pos ? f.box_start[b] : 0, t = f.n_pos ? f.box_start[b + 1] : 0;
+    int64_t s = 0, t = 0;
+    if (f.n_pos) {  // (uniform) both starts loaded before either is used
+      const int32_t s0 = f.box_start[b], s1 = f.box_start[b + 1];
+      s = s0;
+      t = s1;
+    }
     fixup_box(lane, s, t, 0, 0, f.te, f.partials, f.outs, b, f.nout, f.p, f.P, f.norm, f.accumulate);
   }
 }

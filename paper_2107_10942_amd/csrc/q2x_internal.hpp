@@ -168,7 +168,6 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t nblk) {
 // Branch-free in m (lanes of a wavefront hold different orders).
 __device__ __forceinline__ void finalize_store(double* row_generic, int n, int m, double tr, double ti, int norm,
                                                int accumulate) {
-  gdouble* const row = as_global(row_generic);
   const int r = m & 3;
   const double c = (r == 0) ? 1.0 : ((r == 2) ? -1.0 : 0.0);
   const double s = (r == 1) ? -1.0 : ((r == 3) ? 1.0 : 0.0);
@@ -191,19 +190,22 @@ __device__ __forceinline__ void finalize_store(double* row_generic, int n, int m
   if (m == 0) b = 0.0;  // F_n^0 is real; its imaginary part is round-off
   const int ip = n * n + n + m;
   const int im = n * n + n - m;
+  // one 16-byte access per coefficient (rows are 16-byte aligned; the
+  // callers use no LDS, so the generic access costs nothing here)
+  double2* const row2 = reinterpret_cast<double2*>(row_generic);
   if (accumulate) {
-    a += row[2 * ip];
-    b += row[2 * ip + 1];
+    const double2 o = row2[ip];
+    a += o.x;
+    b += o.y;
   }
-  row[2 * ip] = a;
-  row[2 * ip + 1] = b;
+  row2[ip] = make_double2(a, b);
   if (m != 0) {
     if (accumulate) {
-      cc += row[2 * im];
-      d += row[2 * im + 1];
+      const double2 o = row2[im];
+      cc += o.x;
+      d += o.y;
     }
-    row[2 * im] = cc;
-    row[2 * im + 1] = d;
+    row2[im] = make_double2(cc, d);
   }
 }
 
@@ -227,20 +229,59 @@ __device__ __forceinline__ void finish_cut_box(int lane, int64_t t0, int64_t t1,
   const int nct_out = tri(p + 1);
   const int NCT = tri(P + 1);
   const int64_t pstride = (int64_t)nout * NCT;  // partial sums per (tile, slot)
-  for (int gg = lane; gg < nout * nct_out; gg += 64) {
+  const int total = nout * nct_out;
+  // four coefficients per lane at a time, the first two tiles' partials of
+  // all four loaded before any is used (a box spans two tiles but for boxes
+  // longer than a tile), then the rest in tile order; sums in tile order
+  constexpr int U = 4;
+  auto part = [&](int64_t tt, int gg) -> const double2* {
     const int o = gg / nct_out;
     const int g = gg - o * nct_out;
-    double ar = 0.0, ai = 0.0;
-    for (int64_t tt = t0; tt <= t1; ++tt) {
-      const int slot = (tt == t0) ? 1 : 0;
-      cgdouble* pp = as_global(partials) + ((tt * 2 + slot) * pstride + o * NCT + g) * 2;
-      ar += pp[0];
-      ai += pp[1];
+    const int slot = (tt == t0) ? 1 : 0;
+    return reinterpret_cast<const double2*>(partials + ((tt * 2 + slot) * pstride + o * NCT + g) * 2);
+  };
+  for (int g0 = lane; g0 < total; g0 += 64 * U) {
+    double2 va[U], vb[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int gg = g0 + 64 * u;
+      const bool on = gg < total;
+      va[u] = make_double2(0.0, 0.0);
+      vb[u] = make_double2(0.0, 0.0);
+      if (on) {
+        va[u] = *part(t0, gg);
+        vb[u] = *part(t0 + 1, gg);
+      }
     }
-    int n, m;
-    tri_nm(g, n, m);
-    double* const out = (o == 0) ? out0 : ((o == 1) ? out1 : out2);  // (selects: no indexed register array)
-    finalize_store(out + b * (int64_t)ncoef * 2, n, m, ar, ai, norm, accumulate);
+    double ar[U], ai[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ar[u] = va[u].x + vb[u].x;
+      ai[u] = va[u].y + vb[u].y;
+    }
+    for (int64_t tt = t0 + 2; tt <= t1; ++tt) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int gg = g0 + 64 * u;
+        if (gg < total) {
+          const double2 v = *part(tt, gg);
+          ar[u] += v.x;
+          ai[u] += v.y;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int gg = g0 + 64 * u;
+      if (gg < total) {
+        const int o = gg / nct_out;
+        const int g = gg - o * nct_out;
+        int n, m;
+        tri_nm(g, n, m);
+        double* const out = (o == 0) ? out0 : ((o == 1) ? out1 : out2);  // (selects: no indexed register array)
+        finalize_store(out + b * (int64_t)ncoef * 2, n, m, ar[u], ai[u], norm, accumulate);
+      }
+    }
   }
 }
 
