@@ -227,7 +227,9 @@ def serving_workload(dev, n_requests, warmup=50, pool_size=24):
     pool = [configs.serving_job(rng) for _ in range(pool_size)]
     meshes = [serving.pinned_mesh(j) for j in pool]
     free, _ = torch.cuda.mem_get_info(dev)
-    budget = int(0.75 * free)
+    # half the free HBM: the rest is headroom for the caching allocator's
+    # rounding and for blocks cached by earlier phases
+    budget = int(0.5 * free)
 
     def requests(n, rate, seed):
         r = np.random.default_rng(seed)
@@ -260,6 +262,7 @@ def serving_workload(dev, n_requests, warmup=50, pool_size=24):
         out[name] = res
         del srv
         torch.cuda.synchronize()
+        torch.cuda.empty_cache()  # the next phase starts without this one's cached blocks
     return out
 
 

@@ -27,7 +27,7 @@ __global__ __launch_bounds__(256) void q2x_fixup_kernel(FixupArgs f) {
       s = s0;
       t = s1;
     }
-    fixup_box(lane, s, t, 0, 0, f.te, f.partials, f.outs, b, f.nout, f.p, f.P, f.norm, f.accumulate);
+    fixup_box(lane, s, t, 0, f.te, f.partials, f.outs, b, f.nout, f.p, f.norm, f.accumulate);
   }
 }
 
@@ -42,7 +42,8 @@ struct Layout {
   int64_t n_tiles;
 };
 
-Layout layout(int64_t n, int64_t nb, int P, int nout, int prec) {
+// Partial sums are laid out for the requested order p: [n_tiles][2][nout][tri(p+1)][2].
+Layout layout(int64_t n, int64_t nb, int p, int nout, int prec) {
   Layout L;
   L.te = tile_width(n, prec);
   L.n_tiles = (n + L.te - 1) / L.te;
@@ -54,7 +55,7 @@ Layout layout(int64_t n, int64_t nb, int P, int nout, int prec) {
   L.sort = off;
   off += align_up(bucket_scratch_bytes(n, nb));
   L.partials = off;
-  off += align_up((size_t)L.n_tiles * 2 * (size_t)nout * (size_t)tri(P + 1) * 2 * sizeof(double));
+  off += align_up((size_t)L.n_tiles * 2 * (size_t)nout * (size_t)tri(p + 1) * 2 * sizeof(double));
   L.total = off;
   return L;
 }
@@ -129,7 +130,7 @@ q2x_status run(int kind, const double* verts, int64_t n_verts, const int32_t* el
   }
   const int P = bucket_order(p);
   if (P < 0) return Q2X_ERR_UNSUPPORTED;
-  const Layout L = layout(n_elems, n_boxes, P, nout, prec);
+  const Layout L = layout(n_elems, n_boxes, p, nout, prec);
   if (workspace_bytes < L.total) return Q2X_ERR_WORKSPACE;
 
   hipStream_t s = (hipStream_t)stream;
@@ -210,7 +211,6 @@ q2x_status run(int kind, const double* verts, int64_t n_verts, const int32_t* el
     for (int o = 0; o < nout; ++o) f.outs[o] = outs[o];
     f.n_boxes = n_boxes;
     f.p = p;
-    f.P = P;
     f.nout = nout;
     f.norm = norm;
     f.accumulate = a.accumulate;
@@ -265,7 +265,7 @@ size_t q2x_workspace_bytes(int kind, int64_t n_elems, int64_t n_boxes, int p, in
   if (precision != Q2X_FP64 && precision != Q2X_FP32_MIXED) return 0;
   const int P = bucket_order(p);
   if (P < 0) return 0;
-  return layout(n_elems, n_boxes, P, outputs_per_kind(kind), precision).total;
+  return layout(n_elems, n_boxes, p, outputs_per_kind(kind), precision).total;
 }
 
 #define Q2X_ENTRY(name, KIND)                                                                                      \
@@ -308,7 +308,7 @@ q2x_status q2x_tri_both_noalloc(const double* verts, int64_t n_verts, const int3
   if (P < 0) return Q2X_ERR_UNSUPPORTED;
   if (n_tris >= ((int64_t)1 << 31) - 64 || n_boxes >= ((int64_t)1 << 31) - 1) return Q2X_ERR_ARG;
   // the scratch holds the workspace of q2x_tri_both (its status slot unused)
-  if (layout(n_tris, n_boxes, P, 2, precision).total > kNoAllocBytes) return Q2X_ERR_TOO_LARGE;
+  if (layout(n_tris, n_boxes, p, 2, precision).total > kNoAllocBytes) return Q2X_ERR_TOO_LARGE;
   void* ws = scratch_of_current_device();
   if (!ws) return Q2X_ERR_HIP;
   const double* dens[2] = {density_single, density_double};

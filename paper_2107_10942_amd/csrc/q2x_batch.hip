@@ -96,9 +96,8 @@ __global__ __launch_bounds__(256) void batch_fixup(const BatchJob* __restrict__ 
     }
     const BatchJob& J = jobs[lo];
     const int64_t b = gb - J.box_base;
-    fixup_box(lane, box_start[gb], box_start[gb + 1], box_start[J.box_base], J.tile_base, J.te, parts + J.part_off,
-              J.outs,
-              b, J.nout, J.p, J.P, J.norm, J.accumulate);
+    fixup_box(lane, box_start[gb], box_start[gb + 1], box_start[J.box_base], J.te, parts + J.part_off, J.outs, b,
+              J.nout, J.p, J.norm, J.accumulate);
   }
 }
 
@@ -106,7 +105,6 @@ struct Group {
   int kind, prec, P, nout;
   std::vector<int32_t> jobs;
   std::vector<int64_t> tiles;  // prefix, size jobs + 1
-  int64_t part_off;            // doubles
 };
 
 // A launch schedule (see the top of this file).  merge: a bucket group of at
@@ -291,7 +289,6 @@ void build_layout(const q2x_plan* P, const Sched& sc, Layout& L) {
       G.P = Pb;
       G.nout = outputs_of(q.kind);
       G.tiles.push_back(0);
-      G.part_off = 0;
       L.groups.push_back(G);
     }
     Group& G = L.groups[gidx[key]];
@@ -333,13 +330,15 @@ void build_layout(const q2x_plan* P, const Sched& sc, Layout& L) {
     G.jobs.push_back(j);
     G.tiles.push_back(G.tiles.back() + (q.n_elems + J.te - 1) / J.te);
   }
+  // every job's partial sums in a region of its own, laid out for its own
+  // order p (so the layout does not depend on the bucket a job runs in)
   size_t parts = 0;
-  for (Group& G : L.groups) {
-    G.part_off = (int64_t)parts;
-    parts += (size_t)G.tiles.back() * 2 * (size_t)G.nout * (size_t)tri(G.P + 1) * 2;
-    parts = (parts + 31) & ~(size_t)31;  // 256-byte aligned group regions
+  for (BatchJob& J : L.jobs) {
+    J.part_off = (int64_t)parts;
+    const int64_t tiles = (J.n_elems + J.te - 1) / J.te;
+    parts += (size_t)tiles * 2 * (size_t)J.nout * (size_t)tri(J.p + 1) * 2;
+    parts = (parts + 31) & ~(size_t)31;  // 256-byte aligned job regions
   }
-  for (BatchJob& J : L.jobs) J.part_off = L.groups[J.group].part_off;
   L.parts_doubles = parts;
   // workspace layout (the job tables are appended below)
   size_t off = 0;
@@ -447,7 +446,7 @@ hipError_t enqueue(q2x_plan* P, char* ws, const char* tab, int mode, hipStream_t
     TileArgs a{};
     a.keys = skeys;
     a.perm = sperm;
-    a.partials = parts + G.part_off;
+    a.partials = parts;  // (each job's region: BatchJob::part_off)
     a.bjobs = d_jobs;
     a.bgroup_jobs = (const int32_t*)(tab + L.t_gjobs[g]);  // (tab: device memory)
     a.bgroup_tiles = (const int64_t*)(tab + L.t_gtiles[g]);

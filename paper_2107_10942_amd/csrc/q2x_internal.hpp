@@ -55,7 +55,8 @@ struct TileArgs {
   const double* box_center;
   int32_t* box_start;        // [n_boxes + 1] out: start position of each box
   double* outs[3];           // coefficients of output o: [n_boxes][(p+1)^2][2]
-  double* partials;          // [n_tiles][2][nout][tri(P+1)][2] raw sums of boxes cut by tile edges
+  double* partials;          // [n_tiles][2][nout][tri(p+1)][2] raw sums of boxes cut by tile edges (a batch
+                             // job's own region, tiles numbered from the job's first)
   Status* status;
   int64_t n_verts;
   int64_t n_pos;             // number of positions covered by tiles (= n_elems)
@@ -90,7 +91,7 @@ struct BatchJob {
   int64_t elem_base;   // first element in the concatenation of all jobs
   int64_t box_base;    // first global box id
   int64_t tile_base;   // first tile of the job within its group's launch
-  int64_t part_off;    // offset (doubles) of the job's group partials in the workspace
+  int64_t part_off;    // offset (doubles) of the job's partials ([tiles][2][nout][tri(p+1)][2]) in the workspace
   int32_t kind, prec, P, p, norm, accumulate, nout, group, dstride;
   int32_t te;          // elements per tile: the single call's (tile_width), so the sums are bitwise the same
 };
@@ -143,7 +144,6 @@ struct FixupArgs {
   int64_t n_pos;
   int64_t n_boxes;
   int p;
-  int P;                     // bucket order the partials were laid out for
   int nout;                  // outputs per element kind (1; 2 for Q2X_TRI_BOTH; 3 for Q2X_SEGMENT_VEC)
   int norm;
   int accumulate;
@@ -221,14 +221,13 @@ __device__ __forceinline__ void tri_nm(int g, int& n, int& m) {
 // Box b spans tiles t0 < t1: sum its per-tile partial sums in tile order,
 // finalise and store.  Tile t0 left the raw sum of its last segment in slot 1,
 // every later tile that of its first segment in slot 0; a partial block is
-// [tile][slot][nout][tri(P+1)][2] doubles.  One wavefront.
+// [tile][slot][nout][tri(p+1)][2] doubles.  One wavefront.
 __device__ __forceinline__ void finish_cut_box(int lane, int64_t t0, int64_t t1, const double* partials,
                                                double* out0, double* out1, double* out2, int64_t b, int nout, int p,
-                                               int P, int norm, int accumulate) {
+                                               int norm, int accumulate) {
   const int ncoef = (p + 1) * (p + 1);
   const int nct_out = tri(p + 1);
-  const int NCT = tri(P + 1);
-  const int64_t pstride = (int64_t)nout * NCT;  // partial sums per (tile, slot)
+  const int64_t pstride = (int64_t)nout * nct_out;  // partial sums per (tile, slot)
   const int total = nout * nct_out;
   // four coefficients per lane at a time, the first two tiles' partials of
   // all four loaded before any is used (a box spans two tiles but for boxes
@@ -238,7 +237,7 @@ __device__ __forceinline__ void finish_cut_box(int lane, int64_t t0, int64_t t1,
     const int o = gg / nct_out;
     const int g = gg - o * nct_out;
     const int slot = (tt == t0) ? 1 : 0;
-    return reinterpret_cast<const double2*>(partials + ((tt * 2 + slot) * pstride + o * NCT + g) * 2);
+    return reinterpret_cast<const double2*>(partials + ((tt * 2 + slot) * pstride + o * nct_out + g) * 2);
   };
   for (int g0 = lane; g0 < total; g0 += 64 * U) {
     double2 va[U], vb[U];
@@ -286,11 +285,11 @@ __device__ __forceinline__ void finish_cut_box(int lane, int64_t t0, int64_t t1,
 }
 
 // Box b of a sorted range [s, t) whose tiles of te elements start at
-// position base (numbered from tile0 in `partials`): finish it if tile edges
-// cut it; empty boxes get zeros unless accumulating.  One wavefront.
-__device__ __forceinline__ void fixup_box(int lane, int64_t s, int64_t t, int64_t base, int64_t tile0, int te,
+// position base (tile 0 of `partials`): finish it if tile edges cut it; empty
+// boxes get zeros unless accumulating.  One wavefront.
+__device__ __forceinline__ void fixup_box(int lane, int64_t s, int64_t t, int64_t base, int te,
                                           const double* partials, double* const* outs, int64_t b, int nout, int p,
-                                          int P, int norm, int accumulate) {
+                                          int norm, int accumulate) {
   const int ncoef = (p + 1) * (p + 1);
   if (t <= s) {
     if (!accumulate)
@@ -302,8 +301,8 @@ __device__ __forceinline__ void fixup_box(int lane, int64_t s, int64_t t, int64_
   }
   const int64_t t0 = (s - base) / te, t1 = (t - 1 - base) / te;
   if (t0 == t1) return;  // finished by the tile kernel
-  finish_cut_box(lane, tile0 + t0, tile0 + t1, partials, outs[0], nout > 1 ? outs[1] : nullptr,
-                 nout > 2 ? outs[2] : nullptr, b, nout, p, P, norm, accumulate);
+  finish_cut_box(lane, t0, t1, partials, outs[0], nout > 1 ? outs[1] : nullptr, nout > 2 ? outs[2] : nullptr, b,
+                 nout, p, norm, accumulate);
 }
 
 }  // namespace q2x

@@ -418,7 +418,6 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
   constexpr int TE = kTileElems;  // elements per tile (lanes e and e + TE)
   static_assert(2 * TE == kTile, "two lanes per element");
   constexpr int SSTR = (sizeof(T) == 4) ? TE + 4 : TE + 2;
-  constexpr int NCT = tri(P + 1);
   constexpr bool SCALED = PrecInfo<T>::scaled;
   using Plan = ChunkPlan<P, CMAX, NOUT>;
 
@@ -458,6 +457,7 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
   int64_t pos_end = a.n_pos;   // end of the sorted range the tile belongs to
   int64_t key_off = 0;         // sorted keys are key_off + box id
   int64_t elem_off = 0;        // the permutation holds elem_off + element index
+  int64_t ltile = tile;        // the tile's index within its job's partial sums
   const bool batch = (a.bjobs != nullptr);
   if (batch) {
     // this tile's job: tiles [bgroup_tiles[j], bgroup_tiles[j + 1]) belong to job bgroup_jobs[j]
@@ -489,8 +489,10 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
     const int64_t s0 = a.bbox_start[J.box_base];
     pos_end = a.bbox_start[J.box_base + J.n_boxes];
     te = J.te;
-    q0 = s0 + (tile - a.bgroup_tiles[lo]) * te;
+    ltile = tile - a.bgroup_tiles[lo];
+    q0 = s0 + ltile * te;
     elem_off = J.elem_base;  // positions in the concatenation of all jobs
+    a.partials += J.part_off;
   }
   if (q0 >= pos_end) return;  // uniform (past the job's valid elements)
   const int ne = (int)min<int64_t>(te, pos_end - q0);
@@ -642,7 +644,8 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
     const bool act = c < CJ;
     const bool live = act && n <= p;             // a requested coefficient
     const bool wr = live && (h == 0 || m != 0);  // lane h = 1 writes -m for m > 0
-    const int g_coef = o * NCT + tri(n) + m;
+    const int nct_p = tri(p + 1);  // partial sums are laid out for the requested order
+    const int g_coef = o * nct_p + tri(n) + m;
     // Finalisation of a raw tilde sum T = tr + i ti into the +m and -m
     // coefficients (Sec. 3.4, Eqs. (47),(49); symmetry Eq. (12)):
     //   FMM    : F^{+m} = base i^{-m} conj(T), F^{-m} = base i^{-m} T, base = (-1)^n
@@ -663,7 +666,7 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
     const double B1 = im0 ? 0.0 : sq, B2 = im0 ? 0.0 : (h ? cq : -cq);
     const int idx = h ? (n * n + n - m) : (n * n + n + m);
     double* const obase = ((NOUT == 1 || o == 0) ? a.outs[0] : (o == 1 ? a.outs[1] : a.outs[2])) + 2 * idx;
-    double* const pbase = a.partials + (tile * 2 * (int64_t)(NOUT * NCT) + g_coef) * 2;
+    double* const pbase = a.partials + (ltile * 2 * (int64_t)(NOUT * nct_p) + g_coef) * 2;
     const int nsh = (n > shift) ? n - shift : 0;
     // segment state (uniform): first element, box row offset, scale exponents
     int seg = 0;
@@ -698,7 +701,7 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
       const bool head = (seg == 0) && head_open;
       if (head || (sb == ne && tail_open)) {
         if (h == 0 && live) {
-          gdouble* pp = as_global(pbase + (head ? 0 : (int64_t)(NOUT * NCT) * 2));
+          gdouble* pp = as_global(pbase + (head ? 0 : (int64_t)(NOUT * nct_p) * 2));
           pp[0] = tr;
           pp[1] = ti;
         }
