@@ -249,7 +249,9 @@ def serving_workload(dev, n_requests, warmup=50, pool_size=24):
     for resident, name in ((True, "resident_meshes"), (False, "upload_per_request")):
         srv = serving.Server(dev, hbm_budget=budget, max_batch=16, p_fp32_max=32, resident=resident,
                              compute_streams=2)
-        srv.serve(requests(20, 0, 1))  # warm-up (library load, allocator; fills the resident cache)
+        # warm-up: a burst of the measured size (library load, the caching allocator's first
+        # allocations for that many meshes in flight; fills the resident cache)
+        srv.serve(requests(120, 0, 1))
         # capacity: a burst of requests all present at t = 0
         burst = srv.serve(requests(120, 0, 2))
         capacity = len(burst) / max(r.done for r in burst)
