@@ -182,20 +182,7 @@ q2x_status run(int kind, const double* verts, int64_t n_verts, const int32_t* el
   a.count_bad_ids = (flags & Q2X_PRESORTED) ? 1 : 0;
   a.te = L.te;
   const int64_t n_tiles = L.n_tiles;
-  // small grids leave the chip latency-bound: there two workgroups share a
-  // tile's chunks (each runs the recursion).  Measured: FP64 gains with every
-  // tile split up to two tiles per SIMD (1,024 SIMDs); FP32, whose recursion
-  // is the cheaper half of a wave, up to half a tile per SIMD.  Between one
-  // and two FP32 tiles per SIMD, some SIMDs would run two whole tiles: split
-  // just enough tiles for 2,048 workgroups, two per SIMD
-  if (prec == Q2X_FP64)
-    a.n_split = (n_tiles <= 2048) ? n_tiles : 0;
-  else if (n_tiles <= 512)
-    a.n_split = n_tiles;
-  else if (n_tiles > 1024 && n_tiles < 2048)
-    a.n_split = 2048 - n_tiles;
-  else
-    a.n_split = 0;
+  a.n_split = split_count(n_tiles, prec);
   if (timing && hipEventRecord(ev.b, s) != hipSuccess) return Q2X_ERR_HIP;
   if (n_tiles > 0) {
     err = launch_tiles(kind, prec, P, a, n_tiles, s);

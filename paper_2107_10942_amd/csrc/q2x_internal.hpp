@@ -154,10 +154,38 @@ struct FixupArgs {
 // the 8 XCDs (each with its own L2); give every XCD one contiguous range of
 // tiles so that neighbouring tiles, which share vertices and box data, hit
 // the same L2.
-__device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t nblk) {
+__host__ __device__ inline int64_t xcd_tile(int64_t bid, int64_t nblk) {
   const int64_t q = nblk / 8, r = nblk % 8;
   const int64_t x = bid % 8, k = bid / 8;
   return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+// Split tiles (two workgroups each) in a launch of n tiles: s of them, spread
+// evenly -- tile t is split iff floor((t+1) s / n) > floor(t s / n) -- so the
+// launch has n + s workgroups and tile t's first virtual id is t + floor(t s / n).
+// The tile, workgroup part (0 or 1) and part count of virtual id v < n + s,
+// in 32-bit arithmetic (the host splits tiles only in launches of at most
+// 2,048 tiles, so (n + s) n fits).  The same function serves the kernel and
+// the host-side check of the mapping.
+__host__ __device__ inline void split_tile(uint32_t v, uint32_t n, uint32_t s, uint32_t& tile, int& part, int& parts) {
+  uint32_t t = v * n / (n + s);  // within one of the answer
+  while (t + 1 < n && (t + 1) + (t + 1) * s / n <= v) ++t;
+  while (t > 0 && t + t * s / n > v) --t;
+  tile = t;
+  part = (int)(v - (t + t * s / n));
+  parts = ((t + 1) * s / n > t * s / n) ? 2 : 1;
+}
+
+// How many tiles of a single call's launch get two workgroups.  Small grids
+// leave the chip latency-bound, and there two workgroups share a tile's chunks
+// (each runs the recursion): FP64 splits every tile of launches of up to
+// 2,048 tiles; FP32 every tile up to 512, and between 1,024 and 2,048 tiles
+// just enough for 2,048 workgroups, two per SIMD.
+inline int64_t split_count(int64_t n_tiles, int prec) {
+  if (prec == Q2X_FP64) return (n_tiles <= 2048) ? n_tiles : 0;
+  if (n_tiles <= 512) return n_tiles;
+  if (n_tiles > 1024 && n_tiles < 2048) return 2048 - n_tiles;
+  return 0;
 }
 
 // Turn the raw tilde box sum T_n^m (sum_e s_e t~_{e,n}^m, m >= 0) into the two

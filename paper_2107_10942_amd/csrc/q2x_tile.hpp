@@ -438,14 +438,10 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
   const int64_t vb = xcd_tile(blockIdx.x, n_tiles + S);
   int64_t tile = vb;
   int wpart = 0, ns = 1;
-  if (S > 0) {  // uniform; the host splits tiles only in launches of at most 2,048 tiles (32-bit products)
-    const uint32_t n = (uint32_t)n_tiles, s2 = (uint32_t)S, v = (uint32_t)vb;
-    uint32_t t = v * n / (n + s2);  // within one of the answer
-    while (t + 1 < n && (t + 1) + (t + 1) * s2 / n <= v) ++t;
-    while (t > 0 && t + t * s2 / n > v) --t;
+  if (S > 0) {  // uniform
+    uint32_t t;
+    split_tile((uint32_t)vb, (uint32_t)n_tiles, (uint32_t)S, t, wpart, ns);
     tile = t;
-    wpart = (int)(v - (t + t * s2 / n));
-    ns = ((t + 1) * s2 / n > t * s2 / n) ? 2 : 1;
   }
   const int lane = threadIdx.x;
   const int el = lane >> 1;        // the lane's element in the tile

@@ -10,6 +10,10 @@ choice of S (csrc/q2x_api.hip) and checks, for every launch of up to 2,199
 tiles in both precisions, that each (tile, half) is covered exactly once and
 that S tiles are split."""
 
+import os
+
+import pytest
+
 U32 = 0xFFFFFFFF
 
 
@@ -85,3 +89,20 @@ def test_headline_launch_spreads_whole_tiles_over_xcds():
         _, _, ns = tile_of(xcd_tile(b, n + s), n, s)
         whole[b % 8] += ns == 1
     assert whole == [64] * 8
+
+
+def test_library_mapping_functions(tmp_path):
+    """The same check through the library's own functions: a host program
+    built from q2x_internal.hpp (xcd_tile, split_tile, split_count -- the code
+    the kernel and the host call) checks every launch of up to 2,199 tiles."""
+    import subprocess
+    here = os.path.dirname(os.path.abspath(__file__))
+    exe = tmp_path / "split_map_check"
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not found")
+    subprocess.run([hipcc, "--offload-arch=gfx950", "-O2", "-std=c++17", "-I", os.path.join(here, "..", "include"),
+                    os.path.join(here, "split_map_check.hip"), "-o", str(exe)], check=True, capture_output=True)
+    r = subprocess.run([str(exe), "2199"], capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "checked 4398 launches" in r.stdout
