@@ -137,8 +137,14 @@ def error_stats(F, R, elem_norms, density, elem_box, boxes, p):
     with np.errstate(divide="ignore", invalid="ignore"):
         sa = np.where(A > 0, dn / A, 0.0)
         nw = np.where(rn > 0, dn / rn, 0.0)
-    return {"scale_aware_max": float(sa.max()), "normwise_median": float(np.median(nw[rn > 0])),
-            "normwise_max": float(nw.max())}
+    live = rn > 0
+    # rows whose own norm is below 1e-6 of their box's scale A are cancellation-dominated: the
+    # normwise error there measures the cancellation, not the method
+    big = live & (rn > 1e-6 * A)
+    return {"scale_aware_max": float(sa.max()), "normwise_median": float(np.median(nw[live])),
+            "normwise_max": float(nw.max()),
+            "normwise_rows_above_1e-5": int(np.sum(nw[live] > 1e-5)), "rows": int(np.sum(live)),
+            "normwise_max_rows_not_cancelled": float(nw[big].max()) if big.any() else 0.0}
 
 
 def other_workloads(dev, reps=20):

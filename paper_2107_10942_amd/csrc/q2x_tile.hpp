@@ -559,6 +559,14 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
   bool head_open = false, tail_open = false;
   if (q0 > 0) head_open = (a.keys[q0 - 1] == a.keys[q0]);
   if (ne == te && q0 + te < pos_end) tail_open = (a.keys[q0 + te] == a.keys[q0 + te - 1]);
+  // segments finished here (valid box, not continued from the previous tile
+  // or into the next) and segments whose raw sums go to the partials (the
+  // first, continued from the previous tile: slot 0; the last, continued into
+  // the next: slot 1)
+  uint64_t cont = head_open ? 1ull : 0ull;
+  if (tail_open) cont |= 1ull << (63 - __clzll(bnd));  // (bit 0 of bnd is always set here)
+  const uint64_t fin_mask = vseg & ~cont;
+  const uint64_t part_mask = vseg & cont;
   const int p = a.p;
   // offset (doubles) of the element's box row in an output, read by the
   // reduction with readlane at segment starts
@@ -682,8 +690,10 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
       else if constexpr (NOUT == 2) return (o == 0) ? es[0] : es[1];
       else return (o == 0) ? es[0] : ((o == 1) ? es[1] : es[2]);
     };
-    auto flush = [&](int sb, double t) Q2X_INLINE {
-      if (!((vseg >> seg) & 1ull)) return;  // uniform: the segment's box id is outside [0, B)
+    auto flush = [&](double t) Q2X_INLINE {
+      const bool fin = (fin_mask >> seg) & 1ull;  // (uniform)
+      const bool prt = (part_mask >> seg) & 1ull;
+      if (!fin && !prt) return;  // uniform: the segment's box id is outside [0, B)
       if constexpr (SCALED) t *= ldexp(invf, nsh * eb + es_of());
       // pair the halves: tr from lane c, ti from lane c + 32, on every lane
       const uint32_t lo = (uint32_t)__double2loint(t), hi = (uint32_t)__double2hiint(t);
@@ -694,9 +704,9 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
       // uniform: the box continues in another tile.  Its raw sum goes to slot
       // 0 (the tile's first segment, continued from the previous tile) or
       // slot 1 (the last segment, continued in the next tile)
-      const bool head = (seg == 0) && head_open;
-      if (head || (sb == ne && tail_open)) {
+      if (prt) {
         if (h == 0 && live) {
+          const bool head = (seg == 0) && head_open;
           gdouble* pp = as_global(pbase + (head ? 0 : (int64_t)(NOUT * nct_p) * 2));
           pp[0] = tr;
           pp[1] = ti;
@@ -762,7 +772,7 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
       static_for<0, BATCH>([&](auto JB) Q2X_INLINE {
         constexpr int j = decltype(JB)::value;
         if ((uc >> j) & 1u) {  // uniform: a segment ends before element b0 + j
-          flush(b0 + j, a0 + a1);
+          flush(a0 + a1);
           a0 = 0.0;
           a1 = 0.0;
           next_segment(b0 + j);
@@ -775,7 +785,7 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
         if constexpr (j == BATCH - 1) load_half(IC<1>{}, bn, cur);
       });
     }
-    flush(ne, a0 + a1);  // the tile's last segment
+    flush(a0 + a1);  // the tile's last segment
     __syncthreads();
   };
   // chunk J, decoded at compile time (natural chunk ends inside the recursion)
