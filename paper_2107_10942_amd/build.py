@@ -53,13 +53,14 @@ def _units():
 
 
 def source_hash() -> str:
-    """Short hash of the sources of the tile kernel (ties stored profiler
-    figures of that kernel to the code they measured)."""
+    """Short hash of the sources and compiler flags of the tile kernel (ties
+    stored profiler figures of that kernel to the code they measured)."""
     import hashlib
     h = hashlib.sha256()
     for f in ("q2x_tile.hpp", "q2x_internal.hpp", "q2x_inst.hip"):
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
+    h.update(" ".join(COMMON + TILE_FLAGS_F32).encode())
     return h.hexdigest()[:16]
 
 
