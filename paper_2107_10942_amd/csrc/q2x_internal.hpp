@@ -259,7 +259,8 @@ __device__ __forceinline__ void finish_cut_box(int lane, int64_t t0, int64_t t1,
   const int total = nout * nct_out;
   // four coefficients per lane at a time, the first two tiles' partials of
   // all four loaded before any is used (a box spans two tiles but for boxes
-  // longer than a tile), then the rest in tile order; sums in tile order
+  // longer than a tile), then the rest in tile order; sums in tile order.
+  // (Eight at a time measured slower: 44 -> 72 VGPRs, 11.1 -> 13.4 us.)
   constexpr int U = 4;
   auto part = [&](int64_t tt, int gg) -> const double2* {
     const int o = gg / nct_out;
