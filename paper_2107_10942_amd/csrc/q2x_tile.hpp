@@ -673,28 +673,35 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
     double* const pbase = a.partials + (ltile * 2 * (int64_t)(NOUT * nct_p) + g_coef) * 2;
     const int nsh = (n > shift) ? n - shift : 0;
     // segment state (uniform): first element, box row offset, scale exponents
+    // segment state, taken when the segment opens so that its flush does not
+    // wait for it: first element, the lane's output address in the segment's
+    // box row and (FP32) its FP64 factor 2^((n - shift) Eb + Es) / (n + depth)!
     int seg = 0;
-    int64_t boff = readlane64(row_off, 0);
-    int eb = 0;
-    int es[NOUT];
-#pragma unroll
-    for (int q = 0; q < NOUT; ++q) es[q] = 0;
-    if constexpr (SCALED) {
-      eb = __builtin_amdgcn_readfirstlane(seg_eb);
-#pragma unroll
-      for (int q = 0; q < NOUT; ++q) es[q] = __builtin_amdgcn_readfirstlane(seg_es[q]);
-    }
-    // this lane's output's Es of the open segment
-    auto es_of = [&]() Q2X_INLINE -> int {
-      if constexpr (NOUT == 1) return es[0];
-      else if constexpr (NOUT == 2) return (o == 0) ? es[0] : es[1];
-      else return (o == 0) ? es[0] : ((o == 1) ? es[1] : es[2]);
+    gdouble* dst = nullptr;
+    double seg_scale = 1.0;
+    auto open_segment = [&](int i) Q2X_INLINE {
+      seg = i;
+      dst = as_global(obase + readlane64(row_off, 2 * i));
+      if constexpr (SCALED) {
+        const int eb = __builtin_amdgcn_readlane(seg_eb, 2 * i);
+        int es = __builtin_amdgcn_readlane(seg_es[0], 2 * i);
+        if constexpr (NOUT >= 2) {
+          const int es1 = __builtin_amdgcn_readlane(seg_es[1], 2 * i);
+          if (o == 1) es = es1;
+        }
+        if constexpr (NOUT >= 3) {
+          const int es2 = __builtin_amdgcn_readlane(seg_es[2], 2 * i);
+          if (o == 2) es = es2;
+        }
+        seg_scale = ldexp(invf, nsh * eb + es);
+      }
     };
+    open_segment(0);
     auto flush = [&](double t) Q2X_INLINE {
       const bool fin = (fin_mask >> seg) & 1ull;  // (uniform)
       const bool prt = (part_mask >> seg) & 1ull;
       if (!fin && !prt) return;  // uniform: the segment's box id is outside [0, B)
-      if constexpr (SCALED) t *= ldexp(invf, nsh * eb + es_of());
+      if constexpr (SCALED) t *= seg_scale;
       // pair the halves: tr from lane c, ti from lane c + 32, on every lane
       const uint32_t lo = (uint32_t)__double2loint(t), hi = (uint32_t)__double2hiint(t);
       const auto slo = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
@@ -715,22 +722,12 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
       }
       if (!wr) return;
       double x = A1 * tr + A2 * ti, y = B1 * tr + B2 * ti;
-      gdouble* dst = as_global(obase + boff);
       if (a.accumulate) {
         x += dst[0];
         y += dst[1];
       }
       dst[0] = x;
       dst[1] = y;
-    };
-    auto next_segment = [&](int i) Q2X_INLINE {
-      seg = i;
-      boff = readlane64(row_off, 2 * i);
-      if constexpr (SCALED) {
-        eb = __builtin_amdgcn_readlane(seg_eb, 2 * i);
-#pragma unroll
-        for (int q = 0; q < NOUT; ++q) es[q] = __builtin_amdgcn_readlane(seg_es[q], 2 * i);
-      }
     };
     const T* pv = stage + ((h ? CMAX : 0) + (act ? c : 0)) * SSTR;
     // Half H (BATCH / 2 consecutive staged values from position off + H BATCH / 2)
@@ -775,7 +772,7 @@ __global__ __launch_bounds__(kTile) void q2x_tile_kernel(TileArgs args, int64_t 
           flush(a0 + a1);
           a0 = 0.0;
           a1 = 0.0;
-          next_segment(b0 + j);
+          open_segment(b0 + j);
         }
         if constexpr (j & 1)
           a1 += (double)cur[j];
