@@ -370,7 +370,7 @@ q2x_status q2x_eval(int kind, const double* verts, int64_t n_verts, const int32_
   a.p = p;
   a.accumulate = (flags & Q2X_ACCUMULATE) ? 1 : 0;
   a.count_bad_ids = presorted ? 1 : 0;
-  const int64_t n_tiles = (n_elems + kTile - 1) / kTile;
+  const int64_t n_tiles = (n_elems + kTileElems - 1) / kTileElems;  // two lanes per element
   if (launch_eval(kind, precision, P, a, n_tiles, s) != hipSuccess) return Q2X_ERR_HIP;
   return Q2X_OK;
 }

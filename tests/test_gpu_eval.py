@@ -49,8 +49,8 @@ def _check(F, job, L, p, prec, label):
 @pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("p", [0, 1, 5, 12, 16, 21, 32])
 def test_eval_parity(kind, prec, p):
-    """Every order bucket (and p below its bucket), 611 elements (9 full tiles
-    and a ragged tail), boxes of very uneven size and 3 empty boxes."""
+    """Every order bucket (and p below its bucket), 611 elements (19 full tiles
+    of 32 elements and a ragged tail of 3), boxes of very uneven size and 3 empty boxes."""
     job = small_job(kind, 611, 30, p, seed=900 + 10 * kind + p)
     L = _local(job.n_boxes, p, seed=kind * 100 + p)
     F, st = _gpu(job, L, p, prec)
