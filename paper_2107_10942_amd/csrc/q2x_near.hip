@@ -14,14 +14,20 @@
 //   M_P(x, y, z) = -atan(x z (R - y) / (R z^2 + y x^2)),
 //   L_P(x, y, z) = -y M_P(x, y, z) - z ln(R + x),  R = sqrt(x^2 + y^2 + z^2).
 // Per edge the two ends combine: the M_P difference is the argument of a
-// product of two complex numbers (one atan2) and the ln difference the log
-// of a ratio.
+// product of two complex numbers and the ln difference the log of a ratio.
+// The three edges' angles add up to the argument of the product of their
+// three complex numbers; one atan2 gives it modulo 2 pi, and the octants of
+// the three factors (each angle known to within pi/8) fix the multiple of
+// 2 pi.  Every edge angle lies in (-pi, pi) (both ends' M_P in (-pi/2, pi/2)).
 // The printed M lacks the factor sign(hs): with h = |hs| the contour sum is
 // the value on the +n side, and M is odd in hs.  R - y and R + x (x < 0) are
-// formed without cancellation as (x^2 + z^2)/(R + y) and (y^2 + z^2)/(R - x);
-// terms with z = 0 vanish.  A target within 1e-12 (longest edge) of the plane
-// counts as on it: h = 0 and M = 0, the principal value (collocation on the
-// element itself, whose computed height is rounding noise).
+// formed without cancellation as (x^2 + z^2)/(R + y) and (y^2 + z^2)/(R - x),
+// the first folded into the angle (both N and D are scaled by R + y > 0), the
+// second kept as a fraction; terms with z = 0 vanish.  R at an edge's ends is
+// the distance to that vertex, shared by the two edges that meet there.  A
+// target within 1e-12 (longest edge) of the plane counts as on it: h = 0 and
+// M = 0, the principal value (collocation on the element itself, whose
+// computed height is rounding noise).
 //
 // One wavefront per target: lanes take the target's pairs in strides of 64,
 // write the per-pair values if asked (the stored near-field matrix) and sum
@@ -50,18 +56,29 @@ struct NearArgs {
 
 constexpr double kInv4PiNear = 0.07957747154594766788;
 
-// One end of an edge (z != 0): M_P = -atan(N / D) with N = x z (R - y) and
-// D = R z^2 + y x^2 >= 0, and R + x, all without cancellation.
+// One end of an edge (z != 0), at distance R from the target: M_P =
+// -atan(N / D) with N = x z (R - y) and D = R z^2 + y x^2 >= 0, here both
+// times R + y (no division, the angle unchanged), and R + x = a / b.
 struct NearEnd {
-  double N, D, Rpx;
+  double N, D, a, b;
 };
-__device__ __forceinline__ NearEnd near_end(double x, double y, double z) {
-  const double R = sqrt(x * x + y * y + z * z);
+__device__ __forceinline__ NearEnd near_end(double x, double y, double z, double R) {
+  const double x2 = x * x, z2 = z * z;
   NearEnd e;
-  e.N = x * z * ((x * x + z * z) / (R + y));                 // R - y = (x^2 + z^2)/(R + y), y >= 0
-  e.D = R * z * z + y * x * x;
-  e.Rpx = (x >= 0.0) ? R + x : (y * y + z * z) / (R - x);  // > 0 for z != 0
+  e.N = x * z * (x2 + z2);
+  e.D = (R * z2 + y * x2) * (R + y);
+  const bool pos = x >= 0.0;
+  e.a = pos ? R + x : y * y + z2;  // > 0 for z != 0
+  e.b = pos ? 1.0 : R - x;
   return e;
+}
+
+// The angle of c + i s (in (-pi, pi)) to within pi/8: the centre of its octant.
+__device__ __forceinline__ double octant_centre(double c, double s) {
+  constexpr double k8 = 0.39269908169872415481;  // pi / 8
+  const double as = fabs(s), ac = fabs(c);
+  const double m = (c >= 0.0) ? (as <= ac ? 1.0 : 3.0) : (as >= ac ? 5.0 : 7.0);
+  return copysign(m * k8, s);
 }
 
 // Cross product without contraction into FMAs: parallel edge vectors (a
@@ -97,7 +114,16 @@ __device__ bool near_pair(const double* r, const double (&X)[3][3], double& L, d
   double hs = (r[0] - X[0][0]) * nx + (r[1] - X[0][1]) * ny + (r[2] - X[0][2]) * nz;
   if (fabs(hs) <= 1e-12 * sqrt(l2max)) hs = 0.0;
   const double h = fabs(hs);
-  double sL = 0.0, sM = 0.0;
+  // distances to the vertices (R at both ends of every edge)
+  double rho[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double dx = r[0] - X[k][0], dy = r[1] - X[k][1], dz = r[2] - X[k][2];
+    rho[k] = sqrt(dx * dx + dy * dy + dz * dz);
+  }
+  double sL = 0.0;            // sum of -z_q ln(ratio_q)
+  double Pr = 1.0, Pi = 0.0;  // product of the edges' complex numbers
+  double est = 0.0;           // sum of their octant centres
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     const int q1 = (q + 1) % 3;
@@ -111,16 +137,26 @@ __device__ bool near_pair(const double* r, const double (&X)[3][3], double& L, d
     const double xq = dx * ix + dy * iy + dz * iz;
     const double zq = dx * mx + dy * my + dz * mz;
     if (zq == 0.0) continue;  // both ends' terms vanish
-    // M_P(l - x) - M_P(-x) = atan(N0/D0) - atan(N1/D1) = arg((D0 + i N0) conj(D1 + i N1)),
-    // exact for D0, D1 >= 0 (both angles in [-pi/2, pi/2]); one atan2 and one
-    // log of a ratio per edge instead of two of each
-    const NearEnd e1 = near_end(l - xq, h, zq), e0 = near_end(-xq, h, zq);
-    // (N and D scale as the cube of the coordinates: their products stay in
-    // range for coordinates below ~1e50)
-    const double dm = atan2(e0.N * e1.D - e0.D * e1.N, e0.D * e1.D + e0.N * e1.N);
-    sM += dm;
-    sL += -h * dm - zq * log(e1.Rpx / e0.Rpx);
+    // M_P(l - x) - M_P(-x) = arg((D0 + i N0) conj(D1 + i N1))
+    const NearEnd e1 = near_end(l - xq, h, zq, rho[q1]), e0 = near_end(-xq, h, zq, rho[q]);
+    double c = e0.D * e1.D + e0.N * e1.N, sn = e0.N * e1.D - e0.D * e1.N;
+    est += octant_centre(c, sn);
+    // scale to magnitude ~1 (exact) so that the product stays in range
+    const int ex2 = __builtin_amdgcn_frexp_exp(fmax(fabs(c), fabs(sn)));
+    c = ldexp(c, -ex2);
+    sn = ldexp(sn, -ex2);
+    const double pr = Pr * c - Pi * sn, pi = Pr * sn + Pi * c;
+    Pr = pr;
+    Pi = pi;
+    // ln(R1 + x1) - ln(R0 + x0), x1 = l - x_q, x0 = -x_q
+    sL -= zq * log((e1.a * e0.b) / (e0.a * e1.b));
   }
+  // the sum of the edge angles: atan2 of the product plus the multiple of
+  // 2 pi that brings it nearest the octant estimate (within 3 pi / 8)
+  constexpr double k2pi = 6.28318530717958647692;
+  const double phi = atan2(Pi, Pr);
+  const double sM = phi + k2pi * rint((est - phi) * (1.0 / k2pi));
+  sL -= h * sM;
   L = sL * kInv4PiNear;
   M = (hs > 0.0 ? sM : (hs < 0.0 ? -sM : 0.0)) * kInv4PiNear;
   return true;
