@@ -46,6 +46,11 @@ __device__ __forceinline__ int sq_degree(int idx) {  // n with n^2 <= idx < (n+1
   return n;
 }
 
+template <bool B>
+struct BoolC {
+  static constexpr bool value = B;
+};
+
 // wave-scope ordering of this wavefront's LDS writes before its later reads
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -53,7 +58,7 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 template <int P, int NW>
-__global__ __launch_bounds__(64 * NW) void q2x_m2m_kernel(M2MArgs a) {
+__global__ __launch_bounds__(64 * NW, NW == 4 ? 4 : 1) void q2x_m2m_kernel(M2MArgs a) {
   constexpr int NC = (P + 1) * (P + 1);
   constexpr int NT = tri(P + 1);
   constexpr int PER = (NT + 63) / 64;  // outputs per lane
@@ -88,6 +93,43 @@ __global__ __launch_bounds__(64 * NW) void q2x_m2m_kernel(M2MArgs a) {
     mo[r] = (o < ntri) ? o - tri(no[r]) : 0;
   }
 
+  // per-lane index tables, the same for every child: entry idx = lane + 64 i
+  // of the full-order expansion and its source (order |m|, sign pattern of the
+  // symmetry), and the R entries (j, q >= 0) with triangular index
+  // lane + 64 i and their 1 / j!
+  constexpr int NA = (NC + 63) / 64;
+  constexpr int NR = (NT + 63) / 64;
+  constexpr int kNeg = 1 << 16, kOdd = 1 << 17;
+  int acode[NA];
+#pragma unroll
+  for (int i = 0; i < NA; ++i) {
+    const int idx = lane + 64 * i;
+    acode[i] = -1;
+    if (idx < ncoef) {
+      const int n = sq_degree(idx), m = idx - n * n - n;
+      const int am = m < 0 ? -m : m;
+      acode[i] = (n * n + n + am) | (m < 0 ? kNeg : 0) | ((am & 1) ? kOdd : 0);
+    }
+  }
+  int rjq[NR];  // j << 8 | q, or -1
+#pragma unroll
+  for (int i = 0; i < NR; ++i) {
+    const int o = lane + 64 * i;
+    rjq[i] = -1;
+    if (o < ntri) {
+      const int j = tri_degree(o);
+      rjq[i] = (j << 8) | (o - tri(j));
+    }
+  }
+  // 1 / j! for j <= P (one table per workgroup)
+  __shared__ double s_invf[P + 1];
+  if (threadIdx.x <= P) {
+    double f = 1.0;
+    for (int k = 2; k <= (int)threadIdx.x; ++k) f *= (double)k;
+    s_invf[threadIdx.x] = 1.0 / f;
+  }
+  __syncthreads();
+
   for (int64_t b = blockIdx.x; b < a.n_parent; b += gridDim.x) {
     double accr[PER], acci[PER];
 #pragma unroll
@@ -109,19 +151,21 @@ __global__ __launch_bounds__(64 * NW) void q2x_m2m_kernel(M2MArgs a) {
       const double* in = a.child + (size_t)c * (size_t)ncoef * 2;
       wave_sync();  // this wavefront's reads of the previous child are done
       // the child's expansion, all orders: A^{-m} = (-1)^m conj(A^m)
-      for (int idx = lane; idx < ncoef; idx += 64) {
-        const int n = sq_degree(idx), m = idx - n * n - n;
-        const int am = m < 0 ? -m : m;
-        const int g = n * n + n + am;
-        double re = in[2 * g], im = in[2 * g + 1];
-        if (m < 0) {
-          im = -im;
-          if (am & 1) {
-            re = -re;
+#pragma unroll
+      for (int i = 0; i < NA; ++i) {
+        const int code = acode[i];
+        if (code >= 0) {
+          const int g = code & (kNeg - 1);
+          double re = in[2 * g], im = in[2 * g + 1];
+          if (code & kNeg) {
             im = -im;
+            if (code & kOdd) {
+              re = -re;
+              im = -im;
+            }
           }
+          A[lane + 64 * i] = make_double2(re, im);
         }
-        A[idx] = make_double2(re, im);
       }
       // G_j^q (q >= 0) of the shift at R[j^2 + j + q], degree by degree
       const double xr = 0.5 * dx, xi = 0.5 * dy;  // xi = (d_x + i d_y)/2, eta = conj(xi)
@@ -147,12 +191,13 @@ __global__ __launch_bounds__(64 * NW) void q2x_m2m_kernel(M2MArgs a) {
       }
       wave_sync();
       // R_j^q = (-i)^q G_j^q / j!  (q >= 0, in place; one lane per entry)
-      for (int o = lane; o < ntri; o += 64) {
-        const int j = tri_degree(o), q = o - tri(j);
-        double f = 1.0;
-        for (int i = 2; i <= j; ++i) f *= (double)i;
+#pragma unroll
+      for (int i = 0; i < NR; ++i) {
+        if (rjq[i] < 0) continue;
+        const int j = rjq[i] >> 8, q = rjq[i] & 255;
         const double2 g = R[j * j + j + q];
-        const double gr = g.x / f, gi = g.y / f;
+        const double invf = s_invf[j];
+        const double gr = g.x * invf, gi = g.y * invf;
         double rr, ri;
         switch (q & 3) {
           case 0: rr = gr; ri = gi; break;
@@ -164,47 +209,57 @@ __global__ __launch_bounds__(64 * NW) void q2x_m2m_kernel(M2MArgs a) {
       }
       wave_sync();
       // q < 0: R^{-q} = (-1)^q conj(R^q)
-      for (int o = lane; o < ntri; o += 64) {
-        const int j = tri_degree(o), q = o - tri(j);
+#pragma unroll
+      for (int i = 0; i < NR; ++i) {
+        if (rjq[i] < 0) continue;
+        const int j = rjq[i] >> 8, q = rjq[i] & 255;
         if (q == 0) continue;
         const double2 v = R[j * j + j + q];
         const double sgn = (q & 1) ? -1.0 : 1.0;
         R[j * j + j - q] = make_double2(sgn * v.x, -sgn * v.y);
       }
       wave_sync();
-      // out_n^m += sum_{k<=n} sum_l A_k^l R_{n-k}^{qq}, qq = l - m (FMM) or m - l (MOMENT)
+      // out_n^m += sum_{k<=n} sum_l A_k^l R_{n-k}^{qq}, qq = l - m (FMM) or m - l
+      // (MOMENT); instantiated per normalisation so that the step of qq is a
+      // constant (immediate LDS offsets)
+      auto macs = [&](auto MOMc) {
+        constexpr bool MOM = decltype(MOMc)::value;
+        constexpr int step = MOM ? -1 : 1;
 #pragma unroll
-      for (int r = 0; r < PER; ++r) {
-        const int n = no[r], m = mo[r];
-        if (n < 0 || n > p) continue;
-        double sr[4] = {0.0, 0.0, 0.0, 0.0}, si[4] = {0.0, 0.0, 0.0, 0.0};
-        auto mac = [&](int u, const double2 av, const double2 rv) {
-          sr[u] = fma(av.x, rv.x, sr[u]);
-          sr[u] = fma(-av.y, rv.y, sr[u]);
-          si[u] = fma(av.x, rv.y, si[u]);
-          si[u] = fma(av.y, rv.x, si[u]);
-        };
-        for (int k = 0; k <= n; ++k) {
-          const int j = n - k;
-          const int lo = max(-k, m - j), hi = min(k, m + j);
-          const double2* pa = A + k * k + k;
-          const double2* pr = R + j * j + j;
-          const int step = moment ? -1 : 1;
-          int qq = moment ? (m - lo) : (lo - m);
-          int l = lo;
-          for (; l + 3 <= hi; l += 4, qq += 4 * step) {  // four independent chains
-            const double2 a0 = pa[l], a1 = pa[l + 1], a2 = pa[l + 2], a3 = pa[l + 3];
-            const double2 r0 = pr[qq], r1 = pr[qq + step], r2 = pr[qq + 2 * step], r3 = pr[qq + 3 * step];
-            mac(0, a0, r0);
-            mac(1, a1, r1);
-            mac(2, a2, r2);
-            mac(3, a3, r3);
+        for (int r = 0; r < PER; ++r) {
+          const int n = no[r], m = mo[r];
+          if (n < 0 || n > p) continue;
+          double sr[4] = {0.0, 0.0, 0.0, 0.0}, si[4] = {0.0, 0.0, 0.0, 0.0};
+          auto mac = [&](int u, const double2 av, const double2 rv) {
+            sr[u] = fma(av.x, rv.x, sr[u]);
+            sr[u] = fma(-av.y, rv.y, sr[u]);
+            si[u] = fma(av.x, rv.y, si[u]);
+            si[u] = fma(av.y, rv.x, si[u]);
+          };
+          for (int k = 0; k <= n; ++k) {
+            const int j = n - k;
+            const int lo = max(-k, m - j), hi = min(k, m + j);
+            const double2* pa = A + k * k + k + lo;
+            const double2* pr = R + j * j + j + (MOM ? (m - lo) : (lo - m));
+            int cnt = hi - lo + 1;
+            for (; cnt >= 4; cnt -= 4, pa += 4, pr += 4 * step) {  // four independent chains
+              const double2 a0 = pa[0], a1 = pa[1], a2 = pa[2], a3 = pa[3];
+              const double2 r0 = pr[0], r1 = pr[step], r2 = pr[2 * step], r3 = pr[3 * step];
+              mac(0, a0, r0);
+              mac(1, a1, r1);
+              mac(2, a2, r2);
+              mac(3, a3, r3);
+            }
+            for (; cnt > 0; --cnt, ++pa, pr += step) mac(0, pa[0], pr[0]);
           }
-          for (; l <= hi; ++l, qq += step) mac(0, pa[l], pr[qq]);
+          accr[r] += (sr[0] + sr[1]) + (sr[2] + sr[3]);
+          acci[r] += (si[0] + si[1]) + (si[2] + si[3]);
         }
-        accr[r] += (sr[0] + sr[1]) + (sr[2] + sr[3]);
-        acci[r] += (si[0] + si[1]) + (si[2] + si[3]);
-      }
+      };
+      if (moment)
+        macs(BoolC<true>{});
+      else
+        macs(BoolC<false>{});
     }
     if (lane == 0) s_skip[w] = skipped;
     __syncthreads();  // every wavefront is done with its A and R
