@@ -23,7 +23,9 @@
 // R_j^q(d) of the shift for all orders: the m >= 0 part by the ladder
 // recursion of the vertex harmonic (Sec. 3.4, Eq. (50): G_j = D G_{j-1},
 // G_0 = 1, R_j^q = (-i)^q G_j^q / j!), then q < 0 from Eq. (12).  Lane l owns
-// the outputs (n, m >= 0) with triangular index l, 127 - l, 128 + l, ... and adds
+// the outputs (n, m >= 0) with triangular index T - 1 - l, T - 65 - l, ...
+// (T = (p + 1)(p + 2) / 2: degrees descending, so that the lanes of a round
+// have loops of similar length) and adds
 // sum_{k<=n} sum_l A_k^l R_{n-k}^{+-(l-m)}: two contiguous LDS streams per
 // degree k.  The wavefronts' partial sums meet in LDS in a fixed order.
 #include <math.h>
@@ -82,15 +84,16 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 4 : 1) void q2x_m2m_kernel(M2MAr
     }
   }
 
-  // serpentine assignment (lane, 127 - lane, 128 + lane, ...): the work of an
-  // output grows with its degree, so every lane gets a similar total
-  auto out_index = [&](int r) { return 64 * r + ((r & 1) ? 63 - lane : lane); };
+  // outputs in descending triangular order, 64 per round: the lanes of a
+  // round run their loops in lockstep, and outputs of nearby degrees have
+  // similar loop lengths (the longest output of a round sets its time)
+  auto out_index = [&](int r) { return ntri - 1 - (64 * r + lane); };
   int no[PER], mo[PER];
 #pragma unroll
   for (int r = 0; r < PER; ++r) {
     const int o = out_index(r);
-    no[r] = (o < ntri) ? tri_degree(o) : -1;
-    mo[r] = (o < ntri) ? o - tri(no[r]) : 0;
+    no[r] = (o >= 0) ? tri_degree(o) : -1;
+    mo[r] = (o >= 0) ? o - tri(no[r]) : 0;
   }
 
   // per-lane index tables, the same for every child: entry idx = lane + 64 i
@@ -267,7 +270,7 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 4 : 1) void q2x_m2m_kernel(M2MAr
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
       const int o = out_index(r);
-      if (o < ntri) sbuf[w][0][o] = make_double2(accr[r], acci[r]);
+      if (o >= 0) sbuf[w][0][o] = make_double2(accr[r], acci[r]);
     }
     __syncthreads();
     // fixed-order sum over the wavefronts, write +m and -m = (-1)^m conj(+m)
