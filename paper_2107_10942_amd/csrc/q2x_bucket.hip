@@ -10,6 +10,8 @@
 //                stored digit-major (hist[d * n_chunks + chunk]);
 //   2. rowscan : one workgroup per digit scans its row over the chunks
 //                (exclusive, in place) and stores the row total;
+//                (With at most kRawRowChunks chunks there is no row scan:
+//                every scatter workgroup sums the raw rows it needs itself.)
 //   3. scatter : every element moves to base[d] + row[d][chunk] + its rank
 //                among the earlier elements of its chunk with the same digit
 //                (base = exclusive scan of the 256 row totals, redone in LDS
@@ -36,6 +38,9 @@ constexpr int kBins = 256;
 constexpr int kSortThreads = 256;
 constexpr int kItems = 4;
 constexpr int kChunk = kSortThreads * kItems;  // 1024 elements per workgroup
+// up to this many chunks, the scatter sums the raw chunk histograms itself
+// (each of its threads reads one digit's row) instead of a row-scan kernel
+constexpr int64_t kRawRowChunks = 128;
 
 __device__ __forceinline__ int32_t clamp_key(int32_t k, int64_t nb) {
   return (k < 0 || k >= nb) ? (int32_t)nb : k;
@@ -110,7 +115,8 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter(const int32_t* __r
                                                              const int32_t* __restrict__ rows,
                                                              const int32_t* __restrict__ totals, int64_t n_chunks,
                                                              int32_t* __restrict__ keys_out,
-                                                             int32_t* __restrict__ vals_out, Status* status) {
+                                                             int32_t* __restrict__ vals_out, Status* status,
+                                                             int raw_rows) {
   __shared__ int32_t gbase[kBins];
   __shared__ int32_t running[kBins];
   __shared__ int32_t wcnt[kSortThreads / 64][kBins];
@@ -119,7 +125,21 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter(const int32_t* __r
   const int t = threadIdx.x;
   const int w = t >> 6;
   const int lane = t & 63;
-  {
+  if (raw_rows) {
+    // rows holds the raw chunk histograms (no row scan ran): thread t sums its
+    // digit's row, before this chunk and in total
+    const int32_t* row = rows + (int64_t)t * n_chunks;
+    const int64_t me = blockIdx.x;
+    int32_t before = 0, total = 0;
+#pragma unroll 8
+    for (int64_t c = 0; c < n_chunks; ++c) {
+      const int32_t v = row[c];
+      total += v;
+      before += (c < me) ? v : 0;
+    }
+    const int32_t dbase = block_scan_256(total, sh, nullptr);
+    gbase[t] = dbase + before;
+  } else {
     const int32_t dbase = block_scan_256(totals[t], sh, nullptr);
     gbase[t] = dbase + rows[(int64_t)t * n_chunks + blockIdx.x];
   }
@@ -375,9 +395,12 @@ hipError_t bucket_elements(const int32_t* elem_box, int64_t n, int64_t nb, int32
     const int first = (ps == 0);
     hipLaunchKernelGGL(radix_hist, dim3((unsigned)n_chunks), dim3(kSortThreads), 0, s, kin, n, shift, first, nb, hist,
                        n_chunks, status);
-    hipLaunchKernelGGL(radix_rowscan, dim3(kBins), dim3(kSortThreads), 0, s, hist, n_chunks, totals);
+    // few chunks: every scatter workgroup sums the raw rows itself (one
+    // kernel less per pass); many chunks: the row scan runs once
+    const int raw = (n_chunks <= kRawRowChunks) ? 1 : 0;
+    if (!raw) hipLaunchKernelGGL(radix_rowscan, dim3(kBins), dim3(kSortThreads), 0, s, hist, n_chunks, totals);
     hipLaunchKernelGGL(radix_scatter, dim3((unsigned)n_chunks), dim3(kSortThreads), 0, s, kin, vin, n, shift, first,
-                       nb, hist, totals, n_chunks, ko, vo, status);
+                       nb, hist, totals, n_chunks, ko, vo, status, raw);
     kin = ko;
     vin = vo;
     ko = (ko == ka) ? kb : ka;
