@@ -65,7 +65,18 @@ def source_hash() -> str:
     for f in ("q2x_tile.hpp", "q2x_internal.hpp", "q2x_inst.hip"):
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
-    h.update(" ".join(COMMON + TILE_FLAGS_F32).encode())
+    # the flags without the include directory, an absolute path that depends
+    # on where the tree is checked out
+    flags, skip = [], False
+    for f in COMMON + TILE_FLAGS_F32:
+        if skip:
+            skip = False
+            continue
+        if f == "-I":
+            skip = True
+            continue
+        flags.append(f)
+    h.update(" ".join(flags).encode())
     return h.hexdigest()[:16]
 
 

@@ -189,3 +189,16 @@ def test_build_id_and_tune_cache_files(tmp_path):
         q2x.tune_cache_load(tmp_path / "missing.txt")
     with pytest.raises(q2x.Q2XError):
         q2x.tune_cache_save(tmp_path / "no_such_dir" / "x.txt")
+
+
+def test_source_hash_does_not_depend_on_the_checkout_location(monkeypatch):
+    """The tile-kernel source hash ties stored profiler figures to the code they
+    measured; it must be the same wherever the tree is checked out (the
+    compiler flags carry an absolute include directory)."""
+    from paper_2107_10942_amd import build
+    h = build.source_hash()
+    moved = ["/elsewhere/include" if prev == "-I" else f for prev, f in zip([None] + build.COMMON, build.COMMON)]
+    monkeypatch.setattr(build, "COMMON", moved)
+    assert build.source_hash() == h
+    monkeypatch.setattr(build, "COMMON", moved + ["-DQ2X_SOMETHING_ELSE"])
+    assert build.source_hash() != h  # other flags still count
