@@ -32,6 +32,7 @@
 // One wavefront per target: lanes take the target's pairs in strides of 64,
 // write the per-pair values if asked (the stored near-field matrix) and sum
 // sigma_j L + mu_j M; a butterfly reduction gives the target's potential.
+#include <float.h>
 #include <math.h>
 
 #include "q2x_internal.hpp"
@@ -81,6 +82,19 @@ __device__ __forceinline__ double octant_centre(double c, double s) {
   return copysign(m * k8, s);
 }
 
+// 1 / sqrt(x) for finite x > 0: the hardware estimate refined by two
+// Newton-Raphson steps y <- y + y (1 - x y^2) / 2, each of which squares the
+// relative error (x y is formed first so that nothing underflows).
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double xy = x * y;
+    y = fma(0.5 * y, fma(-xy, y, 1.0), y);
+  }
+  return y;
+}
+
 // Cross product without contraction into FMAs: parallel edge vectors (a
 // zero-area triangle) give exactly 0.
 __device__ __forceinline__ void near_cross(double ux, double uy, double uz, double vx, double vy, double vz,
@@ -92,27 +106,32 @@ __device__ __forceinline__ void near_cross(double ux, double uy, double uz, doub
 }
 
 // L and M of one unit-density triangle at r; returns false for a degenerate
-// (zero-area) triangle (L = M = 0).
+// triangle (zero area, or a cross product beyond the FP64 range): L = M = 0.
 __device__ bool near_pair(const double* r, const double (&X)[3][3], double& L, double& M) {
   const double ux = X[1][0] - X[0][0], uy = X[1][1] - X[0][1], uz = X[1][2] - X[0][2];
   const double vx = X[2][0] - X[0][0], vy = X[2][1] - X[0][1], vz = X[2][2] - X[0][2];
   double cx, cy, cz;
   near_cross(ux, uy, uz, vx, vy, vz, cx, cy, cz);
-  const double J = sqrt(cx * cx + cy * cy + cz * cz);
+  const double c2 = cx * cx + cy * cy + cz * cz;  // (2 area)^2
   L = 0.0;
   M = 0.0;
-  if (!(J > 0.0)) return false;
-  const double iJ = 1.0 / J;
+  if (!(c2 > 0.0) || !(c2 <= DBL_MAX)) return false;  // zero area, or a cross product that overflows
+  const double iJ = rsqrt_nr(c2);
   const double nx = cx * iJ, ny = cy * iJ, nz = cz * iJ;
-  double l2max = 0.0;
+  // edge lengths and their reciprocals (every edge of a triangle of nonzero
+  // area is nonzero)
+  double el[3], eil[3], lmax = 0.0;
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     const int q1 = (q + 1) % 3;
     const double ex = X[q1][0] - X[q][0], ey = X[q1][1] - X[q][1], ez = X[q1][2] - X[q][2];
-    l2max = fmax(l2max, ex * ex + ey * ey + ez * ez);
+    const double e2 = ex * ex + ey * ey + ez * ez;
+    eil[q] = rsqrt_nr(e2);
+    el[q] = e2 * eil[q];
+    lmax = fmax(lmax, el[q]);
   }
   double hs = (r[0] - X[0][0]) * nx + (r[1] - X[0][1]) * ny + (r[2] - X[0][2]) * nz;
-  if (fabs(hs) <= 1e-12 * sqrt(l2max)) hs = 0.0;
+  if (fabs(hs) <= 1e-12 * lmax) hs = 0.0;
   const double h = fabs(hs);
   // distances to the vertices (R at both ends of every edge)
   double rho[3];
@@ -128,8 +147,7 @@ __device__ bool near_pair(const double* r, const double (&X)[3][3], double& L, d
   for (int q = 0; q < 3; ++q) {
     const int q1 = (q + 1) % 3;
     const double ex = X[q1][0] - X[q][0], ey = X[q1][1] - X[q][1], ez = X[q1][2] - X[q][2];
-    const double l = sqrt(ex * ex + ey * ey + ez * ez);
-    const double il = 1.0 / l;
+    const double l = el[q], il = eil[q];
     const double ix = ex * il, iy = ey * il, iz = ez * il;
     // n_q = i_q x n
     const double mx = iy * nz - iz * ny, my = iz * nx - ix * nz, mz = ix * ny - iy * nx;
