@@ -93,9 +93,11 @@ def test_bucket_bit_exact():
     import oracle
     from paper_2107_10942_amd import q2x
     rng = np.random.default_rng(7)
-    # one-pass counting sort up to B + 1 = 1024 bins and n = 2^17 (chunks of 2048), radix passes beyond
+    # one-pass counting sort up to B + 1 = 1024 bins and n = 2^17 (chunks of 2048), radix passes beyond; the
+    # radix scatter sums the raw chunk histograms itself up to 128 chunks of 1024 (131,072 elements) and
+    # takes the row-scan kernel above
     for n, nb in [(0, 5), (1, 1), (63, 3), (1000, 37), (2049, 700), (5000, 300), (131072, 1023), (131073, 1023),
-                  (50000, 1024), (70000, 70000), (200000, 4400)]:
+                  (50000, 1024), (70000, 70000), (131072, 4400), (131073, 4400), (200000, 4400)]:
         eb = rng.integers(-3, nb + 3, size=n).astype(np.int32) if n else np.zeros(0, np.int32)
         perm, bs, ws = q2x.bucket(torch.as_tensor(eb).cuda(), nb)
         f, _, skipped = q2x.status(ws)
