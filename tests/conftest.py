@@ -15,7 +15,7 @@ def pytest_configure(config):
 
 def pytest_collection_modifyitems(config, items):
     # GPU tests cannot run without a device: skip them cleanly on CPU-only hosts
-    # (the round-end GPU run selects them with -m gpu on a real MI355X).
+    # (on an MI355X they run, or are selected alone with -m gpu).
     try:
         import torch
         has_gpu = torch.cuda.is_available()
