@@ -245,13 +245,28 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 4 : 1) void q2x_m2m_kernel(M2MAr
             const double2* pa = A + k * k + k + lo;
             const double2* pr = R + j * j + j + (MOM ? (m - lo) : (lo - m));
             int cnt = hi - lo + 1;
-            for (; cnt >= 4; cnt -= 4, pa += 4, pr += 4 * step) {  // four independent chains
-              const double2 a0 = pa[0], a1 = pa[1], a2 = pa[2], a3 = pa[3];
-              const double2 r0 = pr[0], r1 = pr[step], r2 = pr[2 * step], r3 = pr[3 * step];
+            if (cnt >= 4) {  // four independent chains; the next block's reads issued before this block's FMAs
+              double2 a0 = pa[0], a1 = pa[1], a2 = pa[2], a3 = pa[3];
+              double2 r0 = pr[0], r1 = pr[step], r2 = pr[2 * step], r3 = pr[3 * step];
+              for (; cnt >= 8; cnt -= 4) {
+                pa += 4;
+                pr += 4 * step;
+                const double2 b0 = pa[0], b1 = pa[1], b2 = pa[2], b3 = pa[3];
+                const double2 t0 = pr[0], t1 = pr[step], t2 = pr[2 * step], t3 = pr[3 * step];
+                mac(0, a0, r0);
+                mac(1, a1, r1);
+                mac(2, a2, r2);
+                mac(3, a3, r3);
+                a0 = b0; a1 = b1; a2 = b2; a3 = b3;
+                r0 = t0; r1 = t1; r2 = t2; r3 = t3;
+              }
               mac(0, a0, r0);
               mac(1, a1, r1);
               mac(2, a2, r2);
               mac(3, a3, r3);
+              pa += 4;
+              pr += 4 * step;
+              cnt -= 4;
             }
             for (; cnt > 0; --cnt, ++pa, pr += step) mac(0, pa[0], pr[0]);
           }
