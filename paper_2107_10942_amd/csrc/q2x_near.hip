@@ -180,7 +180,11 @@ __device__ bool near_pair(const double* r, const double (&X)[3][3], double& L, d
   return true;
 }
 
-__global__ __launch_bounds__(256) void q2x_near_kernel(NearArgs a) {
+// Three wavefronts per SIMD (at most 168 VGPRs, a few spilled): the pairs'
+// dependent loads and FP64 chains need the extra wavefront to hide latency
+// (measured: 0.98 -> 0.90 ms at 25.2M pairs; four per SIMD spill heavily and
+// run 1.45 ms).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void q2x_near_kernel(NearArgs a) {
   const int lane = threadIdx.x & 63;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
