@@ -60,7 +60,7 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 template <int P, int NW>
-__global__ __launch_bounds__(64 * NW, NW == 4 ? 4 : 1) void q2x_m2m_kernel(M2MArgs a) {
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW >= 4 ? 4 : 1))) void q2x_m2m_kernel(M2MArgs a) {
   constexpr int NC = (P + 1) * (P + 1);
   constexpr int NT = tri(P + 1);
   constexpr int PER = (NT + 63) / 64;  // outputs per lane
@@ -330,29 +330,33 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 4 : 1) void q2x_m2m_kernel(M2MAr
   }
 }
 
+template <int PP, int NWV>
+hipError_t launch_m2m_nw(const M2MArgs& a, int64_t blocks, hipStream_t s) {
+  hipLaunchKernelGGL((q2x_m2m_kernel<PP, NWV>), dim3((unsigned)blocks), dim3(64 * NWV), 0, s, a);
+  return hipGetLastError();
+}
+
+// Wavefronts per parent: 4 up to P = 20 (2 above, for the LDS), and 8 up to
+// P = 16 when the level has at most 512 parents -- there a parent's ~5-8
+// children then run at once instead of two after another (measured at p = 16:
+// 285 parents 55 -> 45 us, 61 parents 48 -> 32 us; with 1,373 parents the
+// four-wavefront launch stays ahead, 109.5 against 112 us).
 hipError_t launch_m2m(const M2MArgs& a, hipStream_t s) {
   int64_t blocks = a.n_parent;
   if (blocks > 65536) blocks = 65536;
   if (blocks < 1) blocks = 1;
-  const int P = bucket_order(a.p);
-  switch (P) {
-#define Q2X_M2M_CASE(PP, NWV)                                                                           \
-  case PP:                                                                                               \
-    hipLaunchKernelGGL((q2x_m2m_kernel<PP, NWV>), dim3((unsigned)blocks), dim3(64 * NWV), 0, s, a); \
-    break;
-    Q2X_M2M_CASE(4, 4)
-    Q2X_M2M_CASE(8, 4)
-    Q2X_M2M_CASE(12, 4)
-    Q2X_M2M_CASE(16, 4)
-    Q2X_M2M_CASE(20, 4)
-    Q2X_M2M_CASE(24, 2)
-    Q2X_M2M_CASE(28, 2)
-    Q2X_M2M_CASE(32, 2)
-#undef Q2X_M2M_CASE
-    default:
-      return hipErrorInvalidValue;
+  const bool few = a.n_parent <= 512;
+  switch (bucket_order(a.p)) {
+    case 4: return few ? launch_m2m_nw<4, 8>(a, blocks, s) : launch_m2m_nw<4, 4>(a, blocks, s);
+    case 8: return few ? launch_m2m_nw<8, 8>(a, blocks, s) : launch_m2m_nw<8, 4>(a, blocks, s);
+    case 12: return few ? launch_m2m_nw<12, 8>(a, blocks, s) : launch_m2m_nw<12, 4>(a, blocks, s);
+    case 16: return few ? launch_m2m_nw<16, 8>(a, blocks, s) : launch_m2m_nw<16, 4>(a, blocks, s);
+    case 20: return launch_m2m_nw<20, 4>(a, blocks, s);
+    case 24: return launch_m2m_nw<24, 2>(a, blocks, s);
+    case 28: return launch_m2m_nw<28, 2>(a, blocks, s);
+    case 32: return launch_m2m_nw<32, 2>(a, blocks, s);
+    default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 }  // namespace q2x
