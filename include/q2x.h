@@ -419,8 +419,8 @@ const char* q2x_build_id(void);
 /*
  * Read the device status word of the last call that used `workspace`
  * (synchronises `stream`).  device_flags: OR of Q2X_FLAG_*; n_degenerate:
- * number of zero-measure elements; n_skipped: elements skipped for bad box,
- * vertex index, radius or non-finite data.  Either output may be NULL.
+ * number of zero-measure elements; n_skipped: elements skipped for a bad box
+ * id or vertex index or for non-finite data.  Either output may be NULL.
  */
 q2x_status q2x_status_get(const void* workspace, void* stream, uint32_t* device_flags, int64_t* n_degenerate,
                           int64_t* n_skipped);
