@@ -186,7 +186,9 @@ __device__ bool near_pair(const double* r, const double (&X)[3][3], double& L, d
 // run 1.45 ms).
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void q2x_near_kernel(NearArgs a) {
   const int lane = threadIdx.x & 63;
-  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  // blocks in XCD order (each XCD's L2 gets a contiguous run of targets, whose
+  // neighbourhoods share triangles)
+  const int64_t wave = xcd_tile(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   uint32_t flag = 0;
   unsigned long long ndeg = 0, nskip = 0;
